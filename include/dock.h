@@ -1,0 +1,203 @@
+/* dock.h -- C ABI of the MI355X (gfx950) docking hot path.
+ *
+ * The problem follows the muDock mini-app of "Towards High-Performance and
+ * Portable Molecular Docking on CPUs through Vectorization" (arXiv 2509.12232):
+ *   - a receptor whose fixed structure is precomputed into 3-D grid maps, one per
+ *     ligand atom type plus electrostatic and desolvation maps (Sec. V);
+ *   - ligands made of typed, charged atoms joined by a bond tree with rotatable
+ *     bonds (Sec. V, Algorithm 1);
+ *   - a pose (individual) = translation + orientation + one angle per rotatable
+ *     bond (Sec. II, Sec. V);
+ *   - its score = inter energy (map lookups for atoms near the protein) + intra
+ *     energy (ligand atom pairs), Sec. V, Algorithm 2;
+ *   - an evolutionary search for the best-scoring pose with the score as fitness
+ *     (Sec. V), here plain differential evolution.
+ *
+ * Conventions for every entry point:
+ *   - Units: Angstrom, kcal/mol, elementary charge, radians.
+ *   - Every call returns a dock_status; on failure dock_last_error() holds a
+ *     message (thread-local, valid until the next dock_* call on that thread).
+ *   - Argument validation happens on the host before anything is enqueued; a
+ *     failed validation enqueues nothing.
+ *   - "device" pointers are HIP device memory of the handle's device; "host"
+ *     pointers are ordinary host memory.  create_* calls copy what they keep, so
+ *     the caller may free its inputs on return.  Outputs are caller-allocated.
+ *     The library never frees caller memory.
+ *   - stream is a hipStream_t (NULL = the legacy default stream) of the handle's
+ *     device.  Compute calls only enqueue work; the caller synchronises.
+ *   - Handles are immutable after creation, so concurrent compute calls on
+ *     different streams are allowed.  Destroy a handle only after the work that
+ *     uses it has completed.
+ */
+#ifndef DOCK_H
+#define DOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DOCK_OK = 0,
+  DOCK_E_INVALID = 1,     /* bad argument or descriptor */
+  DOCK_E_NOMEM = 2,       /* device allocation failed */
+  DOCK_E_DEVICE = 3,      /* HIP runtime error */
+  DOCK_E_UNSUPPORTED = 4  /* valid input outside what this build supports (e.g. > 96 atoms) */
+} dock_status;
+
+/* Message for the last failure on this thread ("" if none). */
+const char *dock_last_error(void);
+
+/* ABI version, incremented on incompatible changes. */
+int32_t dock_version(void);
+
+typedef struct dock_pocket dock_pocket;    /* maps + force field, on one device */
+typedef struct dock_ligands dock_ligands;  /* preprocessed ligand set, on the pocket's device */
+
+/* Force-field data (host pointers, copied).  The paper names the four terms
+ * (electrostatic, van der Waals, hydrogen bond, desolvation; Algorithm 2) but
+ * gives no constants, so all of them are inputs.  Pair potential between atoms
+ * i, j at distance r' = max(r, r_min):
+ *   vdW/H-bond: min(A r'^-12 - B r'^-p, e_cap), r_eq = (Rii_i+Rii_j)/2,
+ *               eps = sqrt(epsii_i epsii_j); p = 6: A = eps r_eq^12, B = 2 eps r_eq^6;
+ *               p = 10 when hbond[t_i*n_types+t_j]: A = 5 eps r_eq^12, B = 6 eps r_eq^10
+ *   electrostatic: coulomb q_i q_j / (eps(r') r'),
+ *               eps(r) = diel_A + (diel_eps0 - diel_A) / (1 + diel_k exp(-diel_lambda (diel_eps0 - diel_A) r))
+ *   desolvation: (S_i vol_j + S_j vol_i) exp(-r'^2 / (2 sigma^2)), S = solpar + qsolpar |q|
+ * map_cap clamps the maps built by dock_create_pocket_from_receptor. */
+typedef struct {
+  int32_t n_types;                          /* 1..32 */
+  const float *Rii, *epsii, *vol, *solpar;  /* [n_types] */
+  const uint8_t *hbond;                     /* [n_types*n_types], symmetric, 0 or 1 */
+  float coulomb, diel_A, diel_eps0, diel_lambda, diel_k;
+  float sigma, qsolpar, e_cap, r_min, map_cap;
+} dock_forcefield;
+
+/* Grid geometry: dims[d] >= 2 nodes per axis; node (i,j,k) at origin + (i,j,k)*spacing.
+ * Maps are float32 [n_types+2][nz][ny][nx], x fastest: maps 0..n_types-1 are the
+ * per-type maps, map n_types the electrostatic map (per unit charge), map
+ * n_types+1 the desolvation map (per unit |charge|). */
+typedef struct {
+  int32_t n_types;
+  int32_t dims[3];
+  float origin[3];
+  float spacing;
+} dock_grid;
+
+/* Create a pocket from precomputed maps (Sec. V: maps precomputed around the
+ * receptor, AutoGrid-style).  maps: host (maps_on_device = 0) or device (1)
+ * pointer in the layout above.  device: HIP device ordinal.  *out receives the
+ * handle.  Errors: DOCK_E_INVALID (null pointers, n_types mismatch, dims < 2,
+ * spacing <= 0, map larger than 2^31 floats), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t maps_on_device,
+                               const dock_forcefield *ff, int32_t device, dock_pocket **out);
+
+/* Create a pocket by building the maps on the GPU from receptor atoms (the
+ * AutoGrid-like step of Sec. V: a probe of each type at every node, summed over
+ * all receptor atoms with the pair potential above; the electrostatic map is the
+ * Coulomb term per unit probe charge, the desolvation map the qsolpar part per
+ * unit |probe charge|; type and desolvation maps are clamped above at map_cap,
+ * the electrostatic map to [-map_cap, map_cap]).  xyz [n_atoms][3], type
+ * [n_atoms], charge [n_atoms]: host pointers.  Synchronous: returns when the
+ * maps are built.  Errors as dock_create_pocket, plus receptor types out of range. */
+dock_status dock_create_pocket_from_receptor(const dock_grid *grid, const dock_forcefield *ff,
+                                             int32_t n_atoms, const float *xyz, const int32_t *type,
+                                             const float *charge, int32_t device, dock_pocket **out);
+
+/* Copy the pocket's maps (layout above) into maps_out: a device pointer of
+ * (n_types+2)*nx*ny*nz floats.  Enqueued on stream. */
+dock_status dock_pocket_maps(const dock_pocket *pocket, float *maps_out, void *stream);
+
+dock_status dock_destroy_pocket(dock_pocket *pocket);
+
+/* One ligand (host pointers, copied).  Atom 0 is the root: each rotatable bond
+ * moves the side away from atom 0 (Algorithm 1, rotamer fragments). */
+typedef struct {
+  int32_t n_atoms;              /* 1..96 */
+  int32_t n_torsions;           /* 0..32 */
+  const float *xyz;             /* [n_atoms][3] reference conformation */
+  const int32_t *type;          /* [n_atoms] in [0, n_types) */
+  const float *charge;          /* [n_atoms] */
+  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree (rings: DOCK_E_UNSUPPORTED) */
+  const int32_t *torsion_bonds; /* [n_torsions] distinct indices into bonds, neither end of degree 1 */
+} dock_ligand_desc;
+
+/* Preprocess a ligand set for a pocket: root at atom 0, ligand origin at the
+ * centroid of the reference conformation, intra pairs = atom pairs at least four
+ * bonds apart that lie in different rigid fragments (Algorithm 2's pair loop; no
+ * distance cutoff).  Errors: DOCK_E_INVALID (bad tree, torsion on a terminal or
+ * repeated bond, type out of range, n_ligands < 1), DOCK_E_UNSUPPORTED (> 96
+ * atoms, > 32 torsions, bond graph with a cycle), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+dock_status dock_create_ligands(const dock_pocket *pocket, const dock_ligand_desc *ligands,
+                                int32_t n_ligands, dock_ligands **out);
+
+/* Number of intra pairs of ligand lig (host query). */
+dock_status dock_ligand_pair_count(const dock_ligands *ligs, int32_t lig, int32_t *n_pairs);
+
+dock_status dock_destroy_ligands(dock_ligands *ligs);
+
+/* Score n_poses poses (Algorithms 1 and 2 for each): pose p of ligand
+ * pose_ligand[p] is built from genotypes[p*g_stride ...] = t(3), q(4) = (w,x,y,z)
+ * (normalised here; |q|^2 < 1e-24 means identity), theta(n_torsions) in the
+ * ligand's torsion order; then energies[p] = inter + intra in kcal/mol, FP32.
+ * Inter: each atom inside the closed grid box adds the trilinear interpolation
+ * of T_type + q E + |q| D; atoms outside add 0.
+ * pose_ligand: device [n_poses] or NULL (every pose is ligand 0); an index out of
+ * range yields NaN for that pose.  genotypes: device [n_poses][g_stride], g_stride
+ * >= 7 + the largest n_torsions of the set.  energies: device [n_poses].  A pose
+ * with a non-finite gene scores NaN.  n_poses = 0 is a no-op.
+ * Errors: DOCK_E_INVALID (null handles/pointers, g_stride too small, handles of
+ * different devices), DOCK_E_DEVICE (launch failure). */
+dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs,
+                             const int32_t *pose_ligand, const float *genotypes, int32_t g_stride,
+                             int64_t n_poses, float *energies, void *stream);
+
+/* Differential evolution (DE/rand/1/bin, greedy selection) as the evolutionary
+ * search of Sec. V.  Random draws come from Philox4x64-10 (Salmon et al., SC'11)
+ * with key (seed, 0) and counter (individual, generation, ligand, purpose << 32 |
+ * block); ligand l of the set uses ligand id l. */
+typedef struct {
+  int32_t pop_size;         /* >= 4 */
+  int32_t n_generations;    /* >= 0 */
+  uint64_t seed;
+  float F, CR;              /* differential weight, crossover rate */
+  double box_lo[3], box_hi[3];  /* translation bounds (init range and clamp) */
+  int32_t init;             /* 1: draw and score the initial population; 0: resume */
+  int32_t first_generation; /* absolute index of the first generation this call runs */
+} dock_search_params;
+
+/* Initial population: rows [n_ligands][pop_size][g_stride] on device, genes
+ * beyond 7 + n_torsions set to 0.  Translation uniform in the box, orientation a
+ * uniform point of the unit 4-ball (uniform rotation once normalised), torsions
+ * uniform in [-pi, pi). */
+dock_status dock_de_init(const dock_ligands *ligs, const dock_search_params *params, int32_t g_stride,
+                         float *population, void *stream);
+
+/* Trial genotypes of one generation from a population (both device
+ * [n_ligands][pop_size][g_stride]).  Gene j of trial i takes x_r1 + F (x_r2 - x_r3)
+ * (binary64 arithmetic, rounded to float32) when a uniform draw is < CR or
+ * j = j_rand, else x_i; translations are clamped to the box, torsions wrapped
+ * once into (-pi, pi]. */
+dock_status dock_de_trials(const dock_ligands *ligs, const dock_search_params *params, int32_t generation,
+                           int32_t g_stride, const float *population, float *trials, void *stream);
+
+/* Full search.  population [n_ligands][pop_size][g_stride] and pop_energy
+ * [n_ligands][pop_size] (device) are in/out: with init = 1 they are overwritten
+ * by the initial population and its scores; with init = 0 they are the state to
+ * resume from (resume with first_generation = generations already run gives
+ * exactly the result of one uninterrupted run).  best_genotypes
+ * [n_ligands][g_stride] and best_energies [n_ligands] (device) receive the best
+ * member of the final population (ties: lowest index).  target [n_ligands]
+ * (device, may be NULL) and gen_reached [n_ligands] (device, may be NULL,
+ * in/out): gen_reached records the number of completed generations at which the
+ * population best first reached <= target (-1 while not reached; with init = 1
+ * it is reset first).  Errors as dock_score_poses plus bad parameters. */
+dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, const dock_search_params *params,
+                        int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
+                        float *best_energies, const float *target, int32_t *gen_reached, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOCK_H */

@@ -1,0 +1,640 @@
+// api.hip -- host side of the C ABI declared in include/dock.h: argument
+// validation, ligand preprocessing, device memory ownership and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "../../include/dock.h"
+#include "dock_internal.h"
+
+using namespace dock;
+
+// ------------------------------------------------------------------------------ errors
+static thread_local char g_err[512];
+
+static dock_status set_err(dock_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static dock_status hip_err(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) return set_err(DOCK_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_err(DOCK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_err(e_, what); \
+  } while (0)
+
+extern "C" const char *dock_last_error(void) { return g_err; }
+extern "C" int32_t dock_version(void) { return 1; }
+
+namespace {
+
+// Makes `device` current for the scope of an API call.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int device) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != device) err = hipSetDevice(device);
+  }
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  *dst = nullptr;
+  if (src.empty()) return hipMalloc((void **)dst, sizeof(T));  // keep a valid pointer
+  hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ handles
+struct dock_pocket {
+  int device = 0;
+  MapGeom geom{};
+  FFConst ffc{};
+  int n_types = 0;
+  std::vector<float> Rii, epsii, vol, solpar;
+  std::vector<uint8_t> hbond;
+  float coulomb = 0, qsolpar = 0;
+  float *maps = nullptr;
+  int64_t plane = 0;
+};
+
+struct dock_ligands {
+  int device = 0;
+  int n_ligs = 0;
+  int max_atoms = 0, max_tors = 0;
+  std::vector<LigHeader> hdr_host;
+  LigHeader *hdr = nullptr;
+  float4 *atoms = nullptr;
+  int32_t *atom_type = nullptr;
+  TorRec *tors = nullptr;
+  PairRec *pairs = nullptr;
+  LigandsDev view() const { return LigandsDev{hdr, atoms, atom_type, tors, pairs, n_ligs}; }
+};
+
+// ------------------------------------------------------------------------------ pockets
+static dock_status check_ff(const dock_forcefield *ff) {
+  if (!ff) return set_err(DOCK_E_INVALID, "null force field");
+  if (ff->n_types < 1 || ff->n_types > kMaxTypes)
+    return set_err(DOCK_E_INVALID, "n_types must be in 1..%d", kMaxTypes);
+  if (!ff->Rii || !ff->epsii || !ff->vol || !ff->solpar || !ff->hbond)
+    return set_err(DOCK_E_INVALID, "null force-field array");
+  for (int t = 0; t < ff->n_types; ++t)
+    if (!(isfinite(ff->Rii[t]) && isfinite(ff->epsii[t]) && ff->epsii[t] >= 0 && isfinite(ff->vol[t]) &&
+          isfinite(ff->solpar[t])))
+      return set_err(DOCK_E_INVALID, "non-finite or negative force-field entry for type %d", t);
+  for (int a = 0; a < ff->n_types; ++a)
+    for (int b = 0; b < ff->n_types; ++b)
+      if (ff->hbond[a * ff->n_types + b] > 1 || ff->hbond[a * ff->n_types + b] != ff->hbond[b * ff->n_types + a])
+        return set_err(DOCK_E_INVALID, "hbond table must be symmetric 0/1");
+  if (!(ff->sigma > 0) || !(ff->r_min > 0) || !isfinite(ff->e_cap) || !isfinite(ff->coulomb) ||
+      !isfinite(ff->diel_A) || !isfinite(ff->diel_eps0) || !isfinite(ff->diel_lambda) || !isfinite(ff->diel_k) ||
+      !isfinite(ff->qsolpar) || !(ff->map_cap > 0))
+    return set_err(DOCK_E_INVALID, "bad force-field constant");
+  return DOCK_OK;
+}
+
+static dock_status check_grid(const dock_grid *g, int n_types) {
+  if (!g) return set_err(DOCK_E_INVALID, "null grid");
+  if (g->n_types != n_types) return set_err(DOCK_E_INVALID, "grid n_types %d != force field %d", g->n_types, n_types);
+  for (int d = 0; d < 3; ++d)
+    if (g->dims[d] < 2) return set_err(DOCK_E_INVALID, "grid dims must be >= 2");
+  if (!(g->spacing > 0) || !isfinite(g->spacing)) return set_err(DOCK_E_INVALID, "spacing must be > 0");
+  for (int d = 0; d < 3; ++d)
+    if (!isfinite(g->origin[d])) return set_err(DOCK_E_INVALID, "non-finite origin");
+  const double total = (double)g->dims[0] * g->dims[1] * g->dims[2] * (n_types + 2);
+  if (total > 2147483647.0) return set_err(DOCK_E_INVALID, "maps larger than 2^31 values");
+  return DOCK_OK;
+}
+
+static void fill_pocket_ff(dock_pocket *p, const dock_forcefield *ff) {
+  const int nt = ff->n_types;
+  p->n_types = nt;
+  p->Rii.assign(ff->Rii, ff->Rii + nt);
+  p->epsii.assign(ff->epsii, ff->epsii + nt);
+  p->vol.assign(ff->vol, ff->vol + nt);
+  p->solpar.assign(ff->solpar, ff->solpar + nt);
+  p->hbond.assign(ff->hbond, ff->hbond + nt * nt);
+  p->coulomb = ff->coulomb;
+  p->qsolpar = ff->qsolpar;
+  const double LOG2E = 1.4426950408889634;
+  const double B = (double)ff->diel_eps0 - ff->diel_A;
+  FFConst &c = p->ffc;
+  c.e_cap = ff->e_cap;
+  c.rmin2 = (float)((double)ff->r_min * ff->r_min);
+  c.eps0 = ff->diel_eps0;
+  c.Ak = (float)((double)ff->diel_A * ff->diel_k);
+  c.k = ff->diel_k;
+  c.diel_c = (float)(-(double)ff->diel_lambda * B * LOG2E);
+  c.gauss_c = (float)(-LOG2E / (2.0 * (double)ff->sigma * ff->sigma));
+  c.pad = 0;
+}
+
+static void fill_geom(dock_pocket *p, const dock_grid *g) {
+  p->geom = MapGeom{g->dims[0], g->dims[1], g->dims[2], g->n_types, g->origin[0], g->origin[1], g->origin[2],
+                    (float)(1.0 / (double)g->spacing)};
+  p->plane = (int64_t)g->dims[0] * g->dims[1] * g->dims[2];
+}
+
+extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t maps_on_device,
+                                          const dock_forcefield *ff, int32_t device, dock_pocket **out) {
+  if (!out) return set_err(DOCK_E_INVALID, "null out");
+  *out = nullptr;
+  dock_status st = check_ff(ff);
+  if (st) return st;
+  if ((st = check_grid(grid, ff->n_types))) return st;
+  if (!maps) return set_err(DOCK_E_INVALID, "null maps");
+  DeviceScope ds(device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  dock_pocket *p = new dock_pocket();
+  p->device = device;
+  fill_pocket_ff(p, ff);
+  fill_geom(p, grid);
+  const size_t bytes = sizeof(float) * p->plane * (ff->n_types + 2);
+  hipError_t e = hipMalloc((void **)&p->maps, bytes);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->maps, maps, bytes, maps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (p->maps) (void)hipFree(p->maps);
+    delete p;
+    return hip_err(e, "pocket maps");
+  }
+  *out = p;
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_create_pocket_from_receptor(const dock_grid *grid, const dock_forcefield *ff,
+                                                        int32_t n_atoms, const float *xyz, const int32_t *type,
+                                                        const float *charge, int32_t device, dock_pocket **out) {
+  if (!out) return set_err(DOCK_E_INVALID, "null out");
+  *out = nullptr;
+  dock_status st = check_ff(ff);
+  if (st) return st;
+  if ((st = check_grid(grid, ff->n_types))) return st;
+  if (n_atoms < 0 || (n_atoms > 0 && (!xyz || !type || !charge)))
+    return set_err(DOCK_E_INVALID, "bad receptor arrays");
+  const int nt = ff->n_types;
+  std::vector<float4> rec(n_atoms);
+  std::vector<int32_t> rt(type, type + n_atoms);
+  for (int i = 0; i < n_atoms; ++i) {
+    if (type[i] < 0 || type[i] >= nt) return set_err(DOCK_E_INVALID, "receptor atom %d type out of range", i);
+    rec[i] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], charge[i]);
+  }
+  std::vector<float> A(nt * nt), B(nt * nt);
+  std::vector<int32_t> hb(nt * nt);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      const double req = 0.5 * ((double)ff->Rii[a] + ff->Rii[b]);
+      const double eps = sqrt((double)ff->epsii[a] * ff->epsii[b]);
+      const bool h = ff->hbond[a * nt + b] != 0;
+      A[a * nt + b] = (float)((h ? 5.0 : 1.0) * eps * pow(req, 12));
+      B[a * nt + b] = (float)((h ? 6.0 : 2.0) * eps * pow(req, h ? 10 : 6));
+      hb[a * nt + b] = h;
+    }
+  DeviceScope ds(device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  dock_pocket *p = new dock_pocket();
+  p->device = device;
+  fill_pocket_ff(p, ff);
+  fill_geom(p, grid);
+  float4 *d_rec = nullptr;
+  int32_t *d_rt = nullptr, *d_hb = nullptr;
+  float *d_A = nullptr, *d_B = nullptr, *d_sol = nullptr, *d_vol = nullptr;
+  hipError_t e = upload(&d_rec, rec);
+  if (e == hipSuccess) e = upload(&d_rt, rt);
+  if (e == hipSuccess) e = upload(&d_A, A);
+  if (e == hipSuccess) e = upload(&d_B, B);
+  if (e == hipSuccess) e = upload(&d_hb, hb);
+  if (e == hipSuccess) e = upload(&d_sol, p->solpar);
+  if (e == hipSuccess) e = upload(&d_vol, p->vol);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->maps, sizeof(float) * p->plane * (nt + 2));
+  if (e == hipSuccess) {
+    MapBuild m{};
+    m.geom = p->geom;
+    m.n_rec = n_atoms;
+    m.rec = d_rec;
+    m.rec_type = d_rt;
+    m.A = d_A;
+    m.B = d_B;
+    m.hb = d_hb;
+    m.solpar = d_sol;
+    m.vol = d_vol;
+    m.qsolpar = ff->qsolpar;
+    m.coulomb = ff->coulomb;
+    m.e_cap = ff->e_cap;
+    m.map_cap = ff->map_cap;
+    m.rmin2 = p->ffc.rmin2;
+    m.h = grid->spacing;
+    m.ff = p->ffc;
+    m.maps = p->maps;
+    e = launch_build_maps(m, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  }
+  for (void *q : {(void *)d_rec, (void *)d_rt, (void *)d_A, (void *)d_B, (void *)d_hb, (void *)d_sol, (void *)d_vol})
+    if (q) (void)hipFree(q);
+  if (e != hipSuccess) {
+    if (p->maps) (void)hipFree(p->maps);
+    delete p;
+    return hip_err(e, "map build");
+  }
+  *out = p;
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_pocket_maps(const dock_pocket *p, float *maps_out, void *stream) {
+  if (!p || !maps_out) return set_err(DOCK_E_INVALID, "null argument");
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(maps_out, p->maps, sizeof(float) * p->plane * (p->n_types + 2), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream),
+          "copy maps");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_destroy_pocket(dock_pocket *p) {
+  if (!p) return DOCK_OK;
+  DeviceScope ds(p->device);
+  if (p->maps) (void)hipFree(p->maps);
+  delete p;
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ ligands
+namespace {
+
+struct PrepOut {
+  std::vector<float4> atoms;
+  std::vector<int32_t> types;
+  std::vector<TorRec> tors;
+  std::vector<PairRec> pairs;  // 12-6 pairs, then 12-10 pairs
+  int n_hb = 0;
+};
+
+// Root at atom 0; depth-first pre-order renumbering so each rotatable bond's far
+// side is one index range; rigid fragments; pairs >= 4 bonds apart across
+// fragments; per-pair coefficients.
+dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig, PrepOut &o) {
+  const int n = d.n_atoms, nt = d.n_torsions;
+  if (n < 1) return set_err(DOCK_E_INVALID, "ligand %d: n_atoms must be >= 1", lig);
+  if (n > kMaxAtoms) return set_err(DOCK_E_UNSUPPORTED, "ligand %d: %d atoms > %d", lig, n, kMaxAtoms);
+  if (nt < 0) return set_err(DOCK_E_INVALID, "ligand %d: negative n_torsions", lig);
+  if (nt > kMaxTorsions) return set_err(DOCK_E_UNSUPPORTED, "ligand %d: %d torsions > %d", lig, nt, kMaxTorsions);
+  if (nt > n - 1) return set_err(DOCK_E_INVALID, "ligand %d: more torsions than bonds", lig);
+  if (!d.xyz || !d.type || !d.charge || (n > 1 && !d.bonds) || (nt > 0 && !d.torsion_bonds))
+    return set_err(DOCK_E_INVALID, "ligand %d: null array", lig);
+  for (int i = 0; i < n; ++i) {
+    if (d.type[i] < 0 || d.type[i] >= P->n_types) return set_err(DOCK_E_INVALID, "ligand %d: atom type out of range", lig);
+    if (!isfinite(d.xyz[3 * i]) || !isfinite(d.xyz[3 * i + 1]) || !isfinite(d.xyz[3 * i + 2]) || !isfinite(d.charge[i]))
+      return set_err(DOCK_E_INVALID, "ligand %d: non-finite coordinate or charge", lig);
+  }
+  std::vector<std::vector<int>> adj(n);
+  for (int k = 0; k < n - 1; ++k) {
+    const int a = d.bonds[2 * k], b = d.bonds[2 * k + 1];
+    if (a < 0 || a >= n || b < 0 || b >= n || a == b) return set_err(DOCK_E_INVALID, "ligand %d: bad bond %d", lig, k);
+    adj[a].push_back(b);
+    adj[b].push_back(a);
+  }
+  // depth-first pre-order from the root
+  std::vector<int> parent(n, -1), order, pos(n, -1), size(n, 1);
+  order.reserve(n);
+  {
+    std::vector<int> stack{0};
+    pos[0] = 0;
+    std::vector<char> seen(n, 0);
+    seen[0] = 1;
+    while (!stack.empty()) {
+      const int u = stack.back();
+      stack.pop_back();
+      pos[u] = (int)order.size();
+      order.push_back(u);
+      for (int k = (int)adj[u].size() - 1; k >= 0; --k) {
+        const int v = adj[u][k];
+        if (v == parent[u]) continue;
+        if (seen[v]) return set_err(DOCK_E_INVALID, "ligand %d: bonds do not form a tree (rings are not supported)", lig);
+        seen[v] = 1;
+        parent[v] = u;
+        stack.push_back(v);
+      }
+    }
+    if ((int)order.size() != n) return set_err(DOCK_E_INVALID, "ligand %d: bonds do not form a tree", lig);
+    for (int k = n - 1; k > 0; --k) size[parent[order[k]]] += size[order[k]];
+  }
+  // rotatable bonds
+  std::vector<char> rot(n > 1 ? n - 1 : 1, 0);
+  o.tors.clear();
+  for (int k = 0; k < nt; ++k) {
+    const int bi = d.torsion_bonds[k];
+    if (bi < 0 || bi >= n - 1) return set_err(DOCK_E_INVALID, "ligand %d: torsion bond index out of range", lig);
+    if (rot[bi]) return set_err(DOCK_E_INVALID, "ligand %d: repeated torsion bond", lig);
+    rot[bi] = 1;
+    int a = d.bonds[2 * bi], b = d.bonds[2 * bi + 1];
+    if (adj[a].size() < 2 || adj[b].size() < 2)
+      return set_err(DOCK_E_INVALID, "ligand %d: torsion on a terminal bond", lig);
+    if (parent[a] == b) std::swap(a, b);  // a on the root side
+    o.tors.push_back(TorRec{pos[a], pos[b], pos[b] + size[b], k});
+  }
+  // rigid fragments (union-find over the non-rotatable bonds)
+  std::vector<int> uf(n);
+  std::iota(uf.begin(), uf.end(), 0);
+  auto find = [&](int x) {
+    while (uf[x] != x) x = uf[x] = uf[uf[x]];
+    return x;
+  };
+  for (int k = 0; k < n - 1; ++k)
+    if (!rot[k]) uf[find(d.bonds[2 * k])] = find(d.bonds[2 * k + 1]);
+  // bond-graph distances
+  std::vector<int> dist((size_t)n * n, -1), q(n);
+  for (int s = 0; s < n; ++s) {
+    int *ds = &dist[(size_t)s * n];
+    int h = 0, t = 0;
+    ds[s] = 0;
+    q[t++] = s;
+    while (h < t) {
+      const int u = q[h++];
+      for (int v : adj[u])
+        if (ds[v] < 0) ds[v] = ds[u] + 1, q[t++] = v;
+    }
+  }
+  // centred reference conformation, in the new order
+  double c[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) c[k] += d.xyz[3 * i + k];
+  for (int k = 0; k < 3; ++k) c[k] /= n;
+  o.atoms.resize(n);
+  o.types.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const int u = order[i];
+    o.atoms[i] = make_float4((float)(d.xyz[3 * u] - c[0]), (float)(d.xyz[3 * u + 1] - c[1]),
+                             (float)(d.xyz[3 * u + 2] - c[2]), d.charge[u]);
+    o.types[i] = d.type[u];
+  }
+  // pairs with coefficients (computed in binary64, stored as float)
+  std::vector<PairRec> plain, hb;
+  for (int u = 0; u < n; ++u)
+    for (int v = u + 1; v < n; ++v) {
+      if (dist[(size_t)u * n + v] < 4 || find(u) == find(v)) continue;
+      const int tu = d.type[u], tv = d.type[v];
+      const double req = 0.5 * ((double)P->Rii[tu] + P->Rii[tv]);
+      const double eps = sqrt((double)P->epsii[tu] * P->epsii[tv]);
+      const bool h = P->hbond[tu * P->n_types + tv] != 0;
+      const double A = (h ? 5.0 : 1.0) * eps * pow(req, 12);
+      const double B = (h ? 6.0 : 2.0) * eps * pow(req, h ? 10 : 6);
+      const double qu = d.charge[u], qv = d.charge[v];
+      const double Su = (double)P->solpar[tu] + (double)P->qsolpar * fabs(qu);
+      const double Sv = (double)P->solpar[tv] + (double)P->qsolpar * fabs(qv);
+      PairRec r{};
+      r.i = std::min(pos[u], pos[v]);
+      r.j = std::max(pos[u], pos[v]);
+      r.A = (float)A;
+      r.B = (float)B;
+      r.qq = (float)((double)P->coulomb * qu * qv);
+      r.sv = (float)(Su * P->vol[tv] + Sv * P->vol[tu]);
+      (h ? hb : plain).push_back(r);
+    }
+  auto by_ij = [](const PairRec &x, const PairRec &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; };
+  std::sort(plain.begin(), plain.end(), by_ij);
+  std::sort(hb.begin(), hb.end(), by_ij);
+  o.pairs = plain;
+  o.pairs.insert(o.pairs.end(), hb.begin(), hb.end());
+  o.n_hb = (int)hb.size();
+  return DOCK_OK;
+}
+
+}  // namespace
+
+static void free_ligands(dock_ligands *L) {
+  for (void *q : {(void *)L->hdr, (void *)L->atoms, (void *)L->atom_type, (void *)L->tors, (void *)L->pairs})
+    if (q) (void)hipFree(q);
+  delete L;
+}
+
+extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock_ligand_desc *ligands,
+                                           int32_t n_ligands, dock_ligands **out) {
+  if (!out) return set_err(DOCK_E_INVALID, "null out");
+  *out = nullptr;
+  if (!pocket || !ligands) return set_err(DOCK_E_INVALID, "null argument");
+  if (n_ligands < 1) return set_err(DOCK_E_INVALID, "n_ligands must be >= 1");
+  std::vector<LigHeader> hdr(n_ligands);
+  std::vector<float4> atoms;
+  std::vector<int32_t> types;
+  std::vector<TorRec> tors;
+  std::vector<PairRec> pairs;
+  int max_atoms = 1, max_tors = 0;
+  PrepOut o;
+  for (int l = 0; l < n_ligands; ++l) {
+    dock_status st = prep_ligand(pocket, ligands[l], l, o);
+    if (st) return st;
+    LigHeader &h = hdr[l];
+    h.n_atoms = (int)o.atoms.size();
+    h.n_tors = (int)o.tors.size();
+    h.n_pairs = (int)o.pairs.size() - o.n_hb;
+    h.n_pairs_hb = o.n_hb;
+    h.atom_off = (int)atoms.size();
+    h.tor_off = (int)tors.size();
+    h.pair_off = (int)pairs.size();
+    h.pad = 0;
+    if ((double)pairs.size() + o.pairs.size() > 2.0e9) return set_err(DOCK_E_UNSUPPORTED, "ligand set too large");
+    atoms.insert(atoms.end(), o.atoms.begin(), o.atoms.end());
+    types.insert(types.end(), o.types.begin(), o.types.end());
+    tors.insert(tors.end(), o.tors.begin(), o.tors.end());
+    pairs.insert(pairs.end(), o.pairs.begin(), o.pairs.end());
+    max_atoms = std::max(max_atoms, h.n_atoms);
+    max_tors = std::max(max_tors, h.n_tors);
+  }
+  DeviceScope ds(pocket->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  dock_ligands *L = new dock_ligands();
+  L->device = pocket->device;
+  L->n_ligs = n_ligands;
+  L->max_atoms = max_atoms;
+  L->max_tors = max_tors;
+  L->hdr_host = hdr;
+  hipError_t e = upload(&L->hdr, hdr);
+  if (e == hipSuccess) e = upload(&L->atoms, atoms);
+  if (e == hipSuccess) e = upload(&L->atom_type, types);
+  if (e == hipSuccess) e = upload(&L->tors, tors);
+  if (e == hipSuccess) e = upload(&L->pairs, pairs);
+  if (e != hipSuccess) {
+    free_ligands(L);
+    return hip_err(e, "ligand upload");
+  }
+  *out = L;
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_ligand_pair_count(const dock_ligands *L, int32_t lig, int32_t *n_pairs) {
+  if (!L || !n_pairs) return set_err(DOCK_E_INVALID, "null argument");
+  if (lig < 0 || lig >= L->n_ligs) return set_err(DOCK_E_INVALID, "ligand index out of range");
+  *n_pairs = L->hdr_host[lig].n_pairs + L->hdr_host[lig].n_pairs_hb;
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_destroy_ligands(dock_ligands *L) {
+  if (!L) return DOCK_OK;
+  DeviceScope ds(L->device);
+  free_ligands(L);
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ scoring
+static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
+  ScoreLaunch a{};
+  a.L = L->view();
+  a.geom = p->geom;
+  a.ff = p->ffc;
+  a.maps = p->maps;
+  a.lds_atoms = L->max_atoms;
+  return a;
+}
+
+static dock_status check_pair(const dock_pocket *p, const dock_ligands *L) {
+  if (!p || !L) return set_err(DOCK_E_INVALID, "null handle");
+  if (p->device != L->device) return set_err(DOCK_E_INVALID, "pocket and ligands on different devices");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_score_poses(const dock_pocket *p, const dock_ligands *L, const int32_t *pose_ligand,
+                                        const float *genotypes, int32_t g_stride, int64_t n_poses, float *energies,
+                                        void *stream) {
+  dock_status st = check_pair(p, L);
+  if (st) return st;
+  if (n_poses < 0) return set_err(DOCK_E_INVALID, "n_poses must be >= 0");
+  if (n_poses == 0) return DOCK_OK;
+  if (!genotypes || !energies) return set_err(DOCK_E_INVALID, "null genotypes or energies");
+  if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride %d < 7 + %d torsions", g_stride, L->max_tors);
+  if (n_poses > ((int64_t)1 << 37)) return set_err(DOCK_E_INVALID, "n_poses too large");
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  ScoreLaunch a = make_score(p, L);
+  a.pose_ligand = pose_ligand;
+  a.poses_per_ligand = 0;
+  a.genotypes = genotypes;
+  a.g_stride = g_stride;
+  a.n_poses = n_poses;
+  a.energies = energies;
+  HIP_TRY(launch_score(a, (hipStream_t)stream), "score launch");
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ search
+static dock_status check_params(const dock_search_params *q) {
+  if (!q) return set_err(DOCK_E_INVALID, "null params");
+  if (q->pop_size < 4) return set_err(DOCK_E_INVALID, "pop_size must be >= 4");
+  if (q->pop_size > (1 << 20)) return set_err(DOCK_E_INVALID, "pop_size too large");
+  if (q->n_generations < 0) return set_err(DOCK_E_INVALID, "n_generations must be >= 0");
+  if (q->first_generation < 0) return set_err(DOCK_E_INVALID, "first_generation must be >= 0");
+  if (!isfinite(q->F) || !isfinite(q->CR)) return set_err(DOCK_E_INVALID, "non-finite F or CR");
+  for (int d = 0; d < 3; ++d)
+    if (!(q->box_lo[d] <= q->box_hi[d]) || !isfinite(q->box_lo[d]) || !isfinite(q->box_hi[d]))
+      return set_err(DOCK_E_INVALID, "empty or non-finite translation box");
+  return DOCK_OK;
+}
+
+static DEParams de_params(const dock_search_params *q) {
+  DEParams p{};
+  p.pop = q->pop_size;
+  p.n_gen = q->n_generations;
+  p.first_gen = q->first_generation;
+  p.seed = q->seed;
+  p.F = q->F;
+  p.CR = q->CR;
+  for (int d = 0; d < 3; ++d) p.lo[d] = q->box_lo[d], p.hi[d] = q->box_hi[d];
+  return p;
+}
+
+extern "C" dock_status dock_de_init(const dock_ligands *L, const dock_search_params *q, int32_t g_stride,
+                                    float *population, void *stream) {
+  if (!L || !population) return set_err(DOCK_E_INVALID, "null argument");
+  dock_status st = check_params(q);
+  if (st) return st;
+  if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
+  DeviceScope ds(L->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(launch_de_init(L->view(), de_params(q), g_stride, population, (hipStream_t)stream), "de_init launch");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_de_trials(const dock_ligands *L, const dock_search_params *q, int32_t generation,
+                                      int32_t g_stride, const float *population, float *trials, void *stream) {
+  if (!L || !population || !trials) return set_err(DOCK_E_INVALID, "null argument");
+  dock_status st = check_params(q);
+  if (st) return st;
+  if (generation < 0) return set_err(DOCK_E_INVALID, "generation must be >= 0");
+  if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
+  DeviceScope ds(L->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(launch_de_trials(L->view(), de_params(q), generation, g_stride, population, trials, (hipStream_t)stream),
+          "de_trials launch");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                   int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
+                                   float *best_energies, const float *target, int32_t *gen_reached, void *stream) {
+  dock_status st = check_pair(p, L);
+  if (st) return st;
+  if ((st = check_params(q))) return st;
+  if (!population || !pop_energy || !best_genotypes || !best_energies)
+    return set_err(DOCK_E_INVALID, "null output buffer");
+  if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
+  if ((int64_t)q->first_generation + q->n_generations > 0x7fffffff) return set_err(DOCK_E_INVALID, "too many generations");
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const DEParams dp = de_params(q);
+  const int nl = L->n_ligs, P = q->pop_size;
+  const int64_t n = (int64_t)nl * P;
+  ScoreLaunch a = make_score(p, L);
+  a.pose_ligand = nullptr;
+  a.poses_per_ligand = P;
+  a.g_stride = g_stride;
+  a.n_poses = n;
+  const bool track = target && gen_reached;
+  if (q->init) {
+    HIP_TRY(launch_de_init(L->view(), dp, g_stride, population, s), "de_init launch");
+    a.genotypes = population;
+    a.energies = pop_energy;
+    HIP_TRY(launch_score(a, s), "score launch");
+  }
+  if (track) HIP_TRY(launch_de_check(nl, P, pop_energy, target, gen_reached, q->first_generation, q->init, s), "check");
+  if (q->n_generations > 0) {
+    float *trials = nullptr, *trial_e = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&trials, sizeof(float) * n * g_stride, s), "trial buffer");
+    hipError_t e = hipMallocAsync((void **)&trial_e, sizeof(float) * n, s);
+    for (int g = q->first_generation; e == hipSuccess && g < q->first_generation + q->n_generations; ++g) {
+      e = launch_de_trials(L->view(), dp, g, g_stride, population, trials, s);
+      if (e != hipSuccess) break;
+      a.genotypes = trials;
+      a.energies = trial_e;
+      e = launch_score(a, s);
+      if (e != hipSuccess) break;
+      e = launch_de_select(nl, P, g_stride, population, pop_energy, trials, trial_e, track ? target : nullptr,
+                           track ? gen_reached : nullptr, g + 1, s);
+    }
+    if (trial_e) (void)hipFreeAsync(trial_e, s);
+    (void)hipFreeAsync(trials, s);
+    if (e != hipSuccess) return hip_err(e, "search loop");
+  }
+  HIP_TRY(launch_de_best(nl, P, g_stride, population, pop_energy, best_genotypes, best_energies, s), "best");
+  return DOCK_OK;
+}

@@ -1,0 +1,117 @@
+// dock_internal.h -- records shared by the host side of the library and its
+// gfx950 kernels.  Everything the kernels read about a ligand is laid out so a
+// wavefront can fetch it with scalar (uniform) loads.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dock {
+
+constexpr int kMaxAtoms = 96;
+constexpr int kMaxTorsions = 32;
+constexpr int kMaxTypes = 32;
+constexpr int kWave = 64;
+
+// Per ligand.  Atoms are renumbered in depth-first pre-order from the root
+// (atom 0), so every rotatable bond's moving fragment is one contiguous range.
+struct alignas(32) LigHeader {
+  int32_t n_atoms;
+  int32_t n_tors;
+  int32_t n_pairs;     // 12-6 pairs first ...
+  int32_t n_pairs_hb;  // ... then 12-10 pairs
+  int32_t atom_off;    // into atoms[] / atom_type[]
+  int32_t tor_off;     // into tors[]
+  int32_t pair_off;    // into pairs[]
+  int32_t pad;
+};
+
+// Rotatable bond: axis from atom a (root side) to atom lo (the far atom, first of
+// its fragment); the fragment is atoms [lo, hi).  gene = index of its angle in
+// the genotype's torsion block.
+struct alignas(16) TorRec {
+  int32_t a, lo, hi, gene;
+};
+
+// Non-bonded pair with its precomputed coefficients.
+struct alignas(32) PairRec {
+  int32_t i, j;
+  float A, B;    // repulsive / attractive coefficients of the 12-6 or 12-10 term
+  float qq;      // coulomb * q_i * q_j
+  float sv;      // S_i vol_j + S_j vol_i
+  int32_t pad0, pad1;
+};
+
+struct MapGeom {
+  int32_t nx, ny, nz, n_types;
+  float ox, oy, oz, inv_h;
+};
+
+struct FFConst {
+  float e_cap, rmin2;
+  float eps0, Ak;     // dielectric: 1/eps(r) = (1 + k e) / (eps0 + A k e), e = exp(-lambda B r)
+  float k, diel_c;    // diel_c = -lambda * B * log2(e)
+  float gauss_c;      // -log2(e) / (2 sigma^2)
+  float pad;
+};
+
+struct LigandsDev {
+  const LigHeader *hdr;
+  const float4 *atoms;     // x, y, z (centred reference), charge
+  const int32_t *atom_type;
+  const TorRec *tors;
+  const PairRec *pairs;
+  int32_t n_ligs;
+};
+
+struct ScoreLaunch {
+  LigandsDev L;
+  MapGeom geom;
+  FFConst ff;
+  const float *maps;
+  const int32_t *pose_ligand;  // may be null
+  int32_t poses_per_ligand;    // > 0: ligand = pose / poses_per_ligand (pose_ligand ignored)
+  const float *genotypes;
+  int32_t g_stride;
+  int64_t n_poses;
+  float *energies;
+  int32_t lds_atoms;           // atom slots per lane in LDS
+};
+
+// Launchers (one translation unit per kernel family).
+hipError_t launch_score(const ScoreLaunch &a, hipStream_t s);
+
+struct DEParams {
+  int32_t pop, n_gen, first_gen;
+  uint64_t seed;
+  float F, CR;
+  double lo[3], hi[3];
+};
+
+hipError_t launch_de_init(const LigandsDev &L, const DEParams &p, int32_t g_stride, float *pop, hipStream_t s);
+hipError_t launch_de_trials(const LigandsDev &L, const DEParams &p, int32_t gen, int32_t g_stride,
+                            const float *pop, float *trials, hipStream_t s);
+hipError_t launch_de_select(int32_t n_ligs, int32_t pop, int32_t g_stride, float *population,
+                            float *pop_energy, const float *trials, const float *trial_energy,
+                            const float *target, int32_t *gen_reached, int32_t gen_done, hipStream_t s);
+hipError_t launch_de_check(int32_t n_ligs, int32_t pop, const float *pop_energy, const float *target,
+                           int32_t *gen_reached, int32_t gen_done, int32_t reset, hipStream_t s);
+hipError_t launch_de_best(int32_t n_ligs, int32_t pop, int32_t g_stride, const float *population,
+                          const float *pop_energy, float *best_g, float *best_e, hipStream_t s);
+
+struct MapBuild {
+  MapGeom geom;
+  int32_t n_rec;
+  const float4 *rec;       // x, y, z, charge
+  const int32_t *rec_type;
+  // per (probe type, receptor type): A, B and the 12-10 flag; per type: solpar, vol
+  const float *A, *B;
+  const int32_t *hb;
+  const float *solpar, *vol;
+  float qsolpar, coulomb, e_cap, map_cap, rmin2, h;
+  FFConst ff;
+  float *maps;
+};
+
+hipError_t launch_build_maps(const MapBuild &m, hipStream_t s);
+
+}  // namespace dock

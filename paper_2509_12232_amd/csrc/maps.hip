@@ -1,0 +1,79 @@
+// maps.hip -- AutoGrid-like grid-map construction on the GPU (Sec. V: the fixed
+// receptor is turned into per-type, electrostatic and desolvation maps).
+//
+// One thread per grid node; receptor atoms stream through LDS in tiles shared by
+// the 256 threads of a block.  Per-type accumulators live in registers (the
+// loop over types is unrolled to the compile-time maximum and predicated).
+#include "dock_internal.h"
+
+namespace dock {
+
+constexpr int kMapBlock = 256;
+
+__global__ __launch_bounds__(kMapBlock) void build_maps_kernel(MapBuild M) {
+  __shared__ float4 s_rec[kMapBlock];
+  __shared__ int s_type[kMapBlock];
+  const MapGeom &G = M.geom;
+  const int64_t plane = (int64_t)G.nx * G.ny * G.nz;
+  const int64_t node = (int64_t)blockIdx.x * kMapBlock + threadIdx.x;
+  const bool live = node < plane;
+  const int ix = (int)(node % G.nx), iy = (int)((node / G.nx) % G.ny), iz = (int)(node / ((int64_t)G.nx * G.ny));
+  const float h = M.h;
+  const float px = fmaf((float)ix, h, G.ox), py = fmaf((float)iy, h, G.oy), pz = fmaf((float)iz, h, G.oz);
+  const int NT = G.n_types;
+  float T[kMaxTypes];
+#pragma unroll
+  for (int a = 0; a < kMaxTypes; ++a) T[a] = 0.f;
+  float E = 0.f, D = 0.f;
+  for (int base = 0; base < M.n_rec; base += kMapBlock) {
+    const int r = base + threadIdx.x;
+    if (r < M.n_rec) {
+      s_rec[threadIdx.x] = M.rec[r];
+      s_type[threadIdx.x] = M.rec_type[r];
+    }
+    __syncthreads();
+    const int cnt = min(kMapBlock, M.n_rec - base);
+    for (int k = 0; k < cnt; ++k) {
+      const float4 R = s_rec[k];
+      const int tr = s_type[k];
+      const float dx = px - R.x, dy = py - R.y, dz = pz - R.z;
+      const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), M.rmin2);
+      const float ir = __builtin_amdgcn_rsqf(r2);
+      const float ir2 = ir * ir, ir6 = ir2 * ir2 * ir2, ir10 = ir6 * ir2 * ir2, ir12 = ir6 * ir6;
+      const float rr = r2 * ir;
+      const float gs = __builtin_amdgcn_exp2f(r2 * M.ff.gauss_c);
+      const float ex = __builtin_amdgcn_exp2f(rr * M.ff.diel_c);
+      const float inv_eps = fmaf(M.ff.k, ex, 1.f) * __builtin_amdgcn_rcpf(fmaf(M.ff.Ak, ex, M.ff.eps0));
+      E = fmaf(M.coulomb * R.w, ir * inv_eps, E);
+      const float vr = M.vol[tr];
+      D = fmaf(M.qsolpar * vr, gs, D);
+      const float Sr = fmaf(M.qsolpar, fabsf(R.w), M.solpar[tr]);
+#pragma unroll
+      for (int a = 0; a < kMaxTypes; ++a) {
+        if (a < NT) {
+          const int c = a * NT + tr;
+          const float att = M.hb[c] ? ir10 : ir6;
+          const float vdw = fminf(fmaf(M.A[c], ir12, -M.B[c] * att), M.e_cap);
+          const float sv = fmaf(M.solpar[a], vr, Sr * M.vol[a]);
+          T[a] += fmaf(sv, gs, vdw);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+#pragma unroll
+  for (int a = 0; a < kMaxTypes; ++a)
+    if (a < NT) M.maps[a * plane + node] = fminf(T[a], M.map_cap);
+  M.maps[NT * plane + node] = fminf(fmaxf(E, -M.map_cap), M.map_cap);
+  M.maps[(NT + 1) * plane + node] = fminf(D, M.map_cap);
+}
+
+hipError_t launch_build_maps(const MapBuild &m, hipStream_t s) {
+  const int64_t plane = (int64_t)m.geom.nx * m.geom.ny * m.geom.nz;
+  const unsigned blocks = (unsigned)((plane + kMapBlock - 1) / kMapBlock);
+  hipLaunchKernelGGL(build_maps_kernel, dim3(blocks), dim3(kMapBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+}  // namespace dock

@@ -1,0 +1,46 @@
+// score.hip -- batched pose scoring kernel for gfx950.
+//
+// One 64-lane workgroup (one wavefront) scores 64 poses, one per lane.  Poses of
+// one ligand share every uniform load; a wavefront holding poses of several
+// ligands walks them one ligand at a time (each pass masks the other lanes).
+#include "dock_internal.h"
+#include "score_pose.h"
+
+namespace dock {
+
+__global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x;
+  const int64_t pose = (int64_t)blockIdx.x * kWave + lane;
+  if (pose >= A.n_poses) return;
+  int lig;
+  if (A.poses_per_ligand > 0) lig = (int)(pose / A.poses_per_ligand);
+  else lig = A.pose_ligand ? A.pose_ligand[pose] : 0;
+  const bool valid = (lig >= 0) & (lig < A.L.n_ligs);
+  float e = __builtin_nanf("");
+  const float *g = A.genotypes + pose * (int64_t)A.g_stride;
+  float *my = lds + lane;
+  uint64_t todo = __ballot(valid);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int cur = __builtin_amdgcn_readlane(lig, leader);
+    const LigHeader H = A.L.hdr[cur];
+    if (valid && lig == cur) e = score_pose<kWave>(A.L, A.geom, A.ff, A.maps, H, g, my);
+    todo &= ~__ballot(valid && lig == cur);
+  }
+  A.energies[pose] = e;
+}
+
+hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
+  if (a.n_poses <= 0) return hipSuccess;
+  const int64_t blocks = (a.n_poses + kWave - 1) / kWave;
+  const size_t lds = (size_t)a.lds_atoms * 3 * kWave * sizeof(float);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)score_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(score_kernel, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace dock

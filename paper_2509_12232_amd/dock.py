@@ -1,0 +1,262 @@
+"""ctypes binding of ``libdock.so`` (include/dock.h), same names as the C ABI.
+
+Argument marshalling only: every step of the hot path runs in the library's HIP
+kernels.  Device buffers are torch tensors on the pocket's device; their
+``data_ptr()`` and the current HIP stream are handed to the library.  If the
+library has not been built, importing this module raises -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdock.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2509_12232_amd.build.build() "
+                      "(hipcc --offload-arch=gfx950) first")
+
+_lib = C.CDLL(LIB_PATH)
+
+DOCK_OK, DOCK_E_INVALID, DOCK_E_NOMEM, DOCK_E_DEVICE, DOCK_E_UNSUPPORTED = range(5)
+_STATUS = {1: "DOCK_E_INVALID", 2: "DOCK_E_NOMEM", 3: "DOCK_E_DEVICE", 4: "DOCK_E_UNSUPPORTED"}
+
+
+class DockError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _FF(C.Structure):
+    _fields_ = [("n_types", C.c_int32),
+                ("Rii", C.c_void_p), ("epsii", C.c_void_p), ("vol", C.c_void_p), ("solpar", C.c_void_p),
+                ("hbond", C.c_void_p),
+                ("coulomb", C.c_float), ("diel_A", C.c_float), ("diel_eps0", C.c_float),
+                ("diel_lambda", C.c_float), ("diel_k", C.c_float),
+                ("sigma", C.c_float), ("qsolpar", C.c_float), ("e_cap", C.c_float), ("r_min", C.c_float),
+                ("map_cap", C.c_float)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n_types", C.c_int32), ("dims", C.c_int32 * 3), ("origin", C.c_float * 3),
+                ("spacing", C.c_float)]
+
+
+class _LigDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_torsions", C.c_int32), ("xyz", C.c_void_p), ("type", C.c_void_p),
+                ("charge", C.c_void_p), ("bonds", C.c_void_p), ("torsion_bonds", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("pop_size", C.c_int32), ("n_generations", C.c_int32), ("seed", C.c_uint64),
+                ("F", C.c_float), ("CR", C.c_float),
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+                ("init", C.c_int32), ("first_generation", C.c_int32)]
+
+
+_P = C.c_void_p
+_lib.dock_last_error.restype = C.c_char_p
+_lib.dock_version.restype = C.c_int32
+_SIGS = {
+    "dock_create_pocket": [_P, _P, C.c_int32, _P, C.c_int32, _P],
+    "dock_create_pocket_from_receptor": [_P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P],
+    "dock_pocket_maps": [_P, _P, _P],
+    "dock_destroy_pocket": [_P],
+    "dock_create_ligands": [_P, _P, C.c_int32, _P],
+    "dock_ligand_pair_count": [_P, C.c_int32, _P],
+    "dock_destroy_ligands": [_P],
+    "dock_score_poses": [_P, _P, _P, _P, C.c_int32, C.c_int64, _P, _P],
+    "dock_de_init": [_P, _P, C.c_int32, _P, _P],
+    "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
+    "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = C.c_int
+
+
+def _check(st: int):
+    if st != DOCK_OK:
+        raise DockError(st, _lib.dock_last_error().decode())
+
+
+def dock_version() -> int:
+    return int(_lib.dock_version())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype_name: str, what: str):
+    """Device pointer of a contiguous torch tensor of the expected dtype (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a device tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"{what}: expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class _Keep:
+    def __init__(self):
+        self.bufs = []
+
+    def arr(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.bufs.append(a)
+        return C.c_void_p(a.ctypes.data) if a.size else None
+
+
+def _ff_struct(ff, keep: _Keep) -> _FF:
+    return _FF(ff.n_types, keep.arr(ff.Rii, np.float32), keep.arr(ff.epsii, np.float32),
+               keep.arr(ff.vol, np.float32), keep.arr(ff.solpar, np.float32),
+               keep.arr(np.asarray(ff.hbond).reshape(-1), np.uint8),
+               ff.coulomb, ff.diel_A, ff.diel_eps0, ff.diel_lambda, ff.diel_k,
+               ff.sigma, ff.qsolpar, ff.e_cap, ff.r_min, ff.map_cap)
+
+
+def _grid_struct(grid) -> _Grid:
+    return _Grid(grid.n_types, (C.c_int32 * 3)(*grid.dims), (C.c_float * 3)(*grid.origin), grid.spacing)
+
+
+class Pocket:
+    """Owner of a dock_pocket handle."""
+
+    def __init__(self, handle: C.c_void_p, grid, device: int):
+        self.handle = handle
+        self.grid = grid
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.dock_destroy_pocket(self.handle)
+            self.handle = None
+
+
+class Ligands:
+    """Owner of a dock_ligands handle."""
+
+    def __init__(self, handle: C.c_void_p, n: int, max_torsions: int, pocket: Pocket):
+        self.handle = handle
+        self.n = n
+        self.max_torsions = max_torsions
+        self.pocket = pocket  # keeps the pocket alive
+
+    def pair_count(self, lig: int) -> int:
+        out = C.c_int32(0)
+        _check(_lib.dock_ligand_pair_count(self.handle, lig, C.byref(out)))
+        return out.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.dock_destroy_ligands(self.handle)
+            self.handle = None
+
+
+def dock_create_pocket(grid, maps, ff, device: int = 0) -> Pocket:
+    """maps: host numpy array or device tensor, float32 [n_types+2, nz, ny, nx]."""
+    keep = _Keep()
+    F = _ff_struct(ff, keep)
+    G = _grid_struct(grid)
+    out = C.c_void_p()
+    if isinstance(maps, np.ndarray):
+        ptr, on_dev = keep.arr(maps, np.float32), 0
+    else:
+        ptr, on_dev = _dptr(maps, "float32", "maps"), 1
+    _check(_lib.dock_create_pocket(C.byref(G), ptr, on_dev, C.byref(F), device, C.byref(out)))
+    return Pocket(out, grid, device)
+
+
+def dock_create_pocket_from_receptor(grid, ff, receptor, device: int = 0) -> Pocket:
+    keep = _Keep()
+    F = _ff_struct(ff, keep)
+    G = _grid_struct(grid)
+    out = C.c_void_p()
+    n = int(len(receptor.type))
+    _check(_lib.dock_create_pocket_from_receptor(C.byref(G), C.byref(F), n, keep.arr(receptor.xyz, np.float32),
+                                                 keep.arr(receptor.type, np.int32),
+                                                 keep.arr(receptor.charge, np.float32), device, C.byref(out)))
+    return Pocket(out, grid, device)
+
+
+def dock_pocket_maps(pocket: Pocket, maps_out, stream=None):
+    _check(_lib.dock_pocket_maps(pocket.handle, _dptr(maps_out, "float32", "maps_out"), _stream(stream)))
+
+
+def dock_create_ligands(pocket: Pocket, ligands) -> Ligands:
+    keep = _Keep()
+    arr = (_LigDesc * len(ligands))()
+    for i, l in enumerate(ligands):
+        arr[i] = _LigDesc(int(l.xyz.shape[0]), int(len(l.torsion_bonds)), keep.arr(l.xyz, np.float32),
+                          keep.arr(l.type, np.int32), keep.arr(l.charge, np.float32),
+                          keep.arr(l.bonds, np.int32), keep.arr(l.torsion_bonds, np.int32))
+    out = C.c_void_p()
+    _check(_lib.dock_create_ligands(pocket.handle, arr, len(ligands), C.byref(out)))
+    max_t = max(int(len(l.torsion_bonds)) for l in ligands)
+    return Ligands(out, len(ligands), max_t, pocket)
+
+
+def dock_score_poses(pocket: Pocket, ligs: Ligands, genotypes, energies, pose_ligand=None, stream=None):
+    """genotypes: float32 [n, g_stride] device tensor; energies: float32 [n] device tensor."""
+    n = int(genotypes.shape[0])
+    if energies.numel() < n:
+        raise ValueError("energies too small")
+    _check(_lib.dock_score_poses(pocket.handle, ligs.handle, _dptr(pose_ligand, "int32", "pose_ligand"),
+                                 _dptr(genotypes, "float32", "genotypes"), int(genotypes.shape[1]), n,
+                                 _dptr(energies, "float32", "energies"), _stream(stream)))
+
+
+@dataclass
+class SearchParams:
+    pop_size: int
+    n_generations: int
+    seed: int
+    box_lo: tuple
+    box_hi: tuple
+    F: float = 0.5
+    CR: float = 0.9
+    init: int = 1
+    first_generation: int = 0
+
+    def _c(self) -> _Params:
+        return _Params(self.pop_size, self.n_generations, self.seed, self.F, self.CR,
+                       (C.c_double * 3)(*self.box_lo), (C.c_double * 3)(*self.box_hi), self.init,
+                       self.first_generation)
+
+
+def dock_de_init(ligs: Ligands, params: SearchParams, population, stream=None):
+    P = params._c()
+    _check(_lib.dock_de_init(ligs.handle, C.byref(P), int(population.shape[-1]),
+                             _dptr(population, "float32", "population"), _stream(stream)))
+
+
+def dock_de_trials(ligs: Ligands, params: SearchParams, generation: int, population, trials, stream=None):
+    P = params._c()
+    _check(_lib.dock_de_trials(ligs.handle, C.byref(P), generation, int(population.shape[-1]),
+                               _dptr(population, "float32", "population"), _dptr(trials, "float32", "trials"),
+                               _stream(stream)))
+
+
+def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy, best_genotypes,
+                best_energies, target=None, gen_reached=None, stream=None):
+    P = params._c()
+    _check(_lib.dock_search(pocket.handle, ligs.handle, C.byref(P), int(population.shape[-1]),
+                            _dptr(population, "float32", "population"), _dptr(pop_energy, "float32", "pop_energy"),
+                            _dptr(best_genotypes, "float32", "best_genotypes"),
+                            _dptr(best_energies, "float32", "best_energies"), _dptr(target, "float32", "target"),
+                            _dptr(gen_reached, "int32", "gen_reached"), _stream(stream)))

@@ -1,0 +1,165 @@
+"""GPU parity of the differential-evolution search (the paper's evolutionary
+search with the score as fitness, Sec. V): bit-identical random streams and
+trial genotypes against the oracle, exact resume, and best-score distributions."""
+import numpy as np
+import pytest
+
+import synth
+from tests._systems import system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2509_12232_amd import dock
+    return dock
+
+
+def _ligs_cfg2(n):
+    atoms, tors = synth.config_ligand_sizes(2)
+    return [synth.make_ligand(1, i, int(atoms[i]), int(tors[i]), 8) for i in range(n)]
+
+
+def _params(mod, lo, hi, **kw):
+    base = dict(pop_size=64, n_generations=5, seed=1, box_lo=tuple(lo), box_hi=tuple(hi))
+    base.update(kw)
+    return mod.SearchParams(**base)
+
+
+def test_init_population_bit_identical(dk, ora):
+    import torch
+    ff, rec, grid, maps = system(2, grid_n=48)
+    ligands = _ligs_cfg2(6)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    P = 37
+    pop = torch.full((6, P, stride), 9.0, dtype=torch.float32, device="cuda")
+    dk.dock_de_init(ligs, _params(dk, lo, hi, pop_size=P, seed=99), pop)
+    torch.cuda.synchronize()
+    got = pop.cpu().numpy()
+    for l, lig in enumerate(ligands):
+        ref = ora.de_init(lig, _params(ora, lo, hi, pop_size=P, seed=99), l, stride)
+        assert np.array_equal(got[l].view(np.uint32), ref.view(np.uint32)), l
+
+
+def test_trials_bit_identical(dk, ora):
+    import torch
+    ff, rec, grid, maps = system(2, grid_n=48)
+    ligands = _ligs_cfg2(5)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    P = 50
+    rng = np.random.default_rng(3)
+    pop = np.zeros((5, P, stride), np.float32)
+    for l, lig in enumerate(ligands):
+        pop[l] = ora.de_init(lig, _params(ora, lo, hi, pop_size=P), l, stride)
+        pop[l, :, :3] += rng.normal(0, 3, (P, 3)).astype(np.float32)   # some outside the box: clamp path
+    for gen, (F, CR) in enumerate([(0.5, 0.9), (0.8, 0.3), (1.7, 1.0)]):
+        tr = torch.zeros((5, P, stride), dtype=torch.float32, device="cuda")
+        dk.dock_de_trials(ligs, _params(dk, lo, hi, pop_size=P, F=F, CR=CR, seed=5), gen + 3,
+                          torch.from_numpy(pop).cuda(), tr)
+        torch.cuda.synchronize()
+        got = tr.cpu().numpy()
+        for l, lig in enumerate(ligands):
+            ref = ora.de_trials(lig, _params(ora, lo, hi, pop_size=P, F=F, CR=CR, seed=5), l, gen + 3, pop[l])
+            assert np.array_equal(got[l].view(np.uint32), ref.view(np.uint32)), (gen, l)
+
+
+def _run_gpu_search(dk, pocket, ligs, params, n_lig, stride, population=None, pop_energy=None, target=None,
+                    gen_reached=None):
+    import torch
+    P = params.pop_size
+    pop = torch.zeros((n_lig, P, stride), dtype=torch.float32, device="cuda") if population is None \
+        else population.clone()
+    pe = torch.zeros((n_lig, P), dtype=torch.float32, device="cuda") if pop_energy is None else pop_energy.clone()
+    bg = torch.zeros((n_lig, stride), dtype=torch.float32, device="cuda")
+    be = torch.zeros(n_lig, dtype=torch.float32, device="cuda")
+    gr = None
+    if target is not None:
+        gr = torch.full((n_lig,), -1, dtype=torch.int32, device="cuda") if gen_reached is None else gen_reached.clone()
+    dk.dock_search(pocket, ligs, params, pop, pe, bg, be, target=target, gen_reached=gr)
+    torch.cuda.synchronize()
+    return pop, pe, bg, be, gr
+
+
+def test_resume_bit_identical_on_gpu(dk):
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, [lig])
+    lo, hi = synth.pocket_box(grid)
+    full = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=20), 1, 13)
+    a = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=8), 1, 13)
+    b = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=12, init=0, first_generation=8), 1, 13,
+                        population=a[0], pop_energy=a[1])
+    for x, y in zip(full[:4], b[:4]):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def test_search_energies_are_scores_and_improve(dk, ora):
+    """After a GPU search every stored energy is the oracle score of its stored
+    genotype (within tolerance), and the best improves on the initial population."""
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, [lig])
+    lo, hi = synth.pocket_box(grid)
+    p0 = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=0), 1, 13)
+    p = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=100), 1, 13)
+    pop = p[0].cpu().numpy()[0]
+    pe = p[1].cpu().numpy()[0]
+    ref = ora.score_poses(grid, maps, ff, [lig], pop)
+    from tests._systems import assert_energies_match
+    assert_energies_match(pe, ref)
+    assert float(p[3].cpu()[0]) < float(p0[3].cpu()[0])
+    assert float(p[3].cpu()[0]) == pe.min()
+
+
+def test_search_matches_oracle_lockstep_then_distribution(dk, ora):
+    """Config 0 (24 atoms, 6 torsions, 40^3 maps; population 64, 100 generations)
+    for 8 seeds.  Both sides draw the same random streams, so they agree exactly
+    until a near-tie selection flips between FP32 and FP64; the best scores must
+    agree in distribution (medians within 0.1 kcal/mol, two-sample KS p > 0.01)."""
+    from scipy.stats import ks_2samp
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, [lig])
+    lo, hi = synth.pocket_box(grid)
+    gpu_best, ora_best, identical = [], [], 0
+    for seed in range(1, 9):
+        g = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=100, seed=seed), 1, 13)
+        o = ora.search(grid, maps, ff, [lig], _params(ora, lo, hi, n_generations=100, seed=seed), 13)
+        gpu_best.append(float(g[3].cpu()[0]))
+        ora_best.append(float(o["best_energy"][0]))
+        identical += int(np.array_equal(g[0].cpu().numpy(), o["population"]))
+    print("gpu best", np.round(gpu_best, 3), "oracle best", np.round(ora_best, 3), "identical runs", identical)
+    assert abs(np.median(gpu_best) - np.median(ora_best)) < 0.1 or identical >= 4
+    assert ks_2samp(gpu_best, ora_best).pvalue > 0.01
+
+
+def test_gen_reached(dk):
+    import torch
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, [lig])
+    lo, hi = synth.pocket_box(grid)
+    full = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=30), 1, 13)
+    tgt = full[3].clone()
+    r = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=30), 1, 13, target=tgt)
+    gr = int(r[4].cpu()[0])
+    assert 0 <= gr <= 30
+    if gr > 0:
+        part = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=gr - 1), 1, 13)
+        assert float(part[3].cpu()[0]) > float(tgt.cpu()[0])
+    r = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, n_generations=30), 1, 13, target=tgt - 1e4)
+    assert int(r[4].cpu()[0]) == -1

@@ -85,13 +85,24 @@ typedef struct {
   float spacing;
 } dock_grid;
 
+/* Device layout of the maps read by the scoring kernel (the ABI layout above is
+ * always kept as well).  The packed layouts duplicate neighbouring nodes so the
+ * eight corners of a grid cell come from fewer cache lines:
+ *   DOCK_LAYOUT_LINEAR  the ABI layout itself (1x memory);
+ *   DOCK_LAYOUT_ZPAIR   node pairs along z, x-neighbours adjacent (2x);
+ *   DOCK_LAYOUT_YZQUAD  node quads over y and z, x-neighbours adjacent (4x);
+ *   DOCK_LAYOUT_AUTO    the yz-quad layout if its copy fits 240 MiB, else z-pair.
+ * Results do not depend on the layout beyond float rounding of the same terms. */
+enum { DOCK_LAYOUT_AUTO = -1, DOCK_LAYOUT_LINEAR = 0, DOCK_LAYOUT_ZPAIR = 1, DOCK_LAYOUT_YZQUAD = 2 };
+
 /* Create a pocket from precomputed maps (Sec. V: maps precomputed around the
  * receptor, AutoGrid-style).  maps: host (maps_on_device = 0) or device (1)
- * pointer in the layout above.  device: HIP device ordinal.  *out receives the
- * handle.  Errors: DOCK_E_INVALID (null pointers, n_types mismatch, dims < 2,
- * spacing <= 0, map larger than 2^31 floats), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+ * pointer in the layout above.  layout: one of DOCK_LAYOUT_*.  device: HIP
+ * device ordinal.  *out receives the handle.  Synchronous.  Errors:
+ * DOCK_E_INVALID (null pointers, n_types mismatch, dims < 2, spacing <= 0, map
+ * larger than 2^31 floats, unknown layout), DOCK_E_NOMEM, DOCK_E_DEVICE. */
 dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t maps_on_device,
-                               const dock_forcefield *ff, int32_t device, dock_pocket **out);
+                               const dock_forcefield *ff, int32_t layout, int32_t device, dock_pocket **out);
 
 /* Create a pocket by building the maps on the GPU from receptor atoms (the
  * AutoGrid-like step of Sec. V: a probe of each type at every node, summed over
@@ -99,11 +110,16 @@ dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t
  * Coulomb term per unit probe charge, the desolvation map the qsolpar part per
  * unit |probe charge|; type and desolvation maps are clamped above at map_cap,
  * the electrostatic map to [-map_cap, map_cap]).  xyz [n_atoms][3], type
- * [n_atoms], charge [n_atoms]: host pointers.  Synchronous: returns when the
- * maps are built.  Errors as dock_create_pocket, plus receptor types out of range. */
+ * [n_atoms], charge [n_atoms]: host pointers.  layout as dock_create_pocket.
+ * Synchronous: returns when the maps are built.  Errors as dock_create_pocket,
+ * plus receptor types out of range. */
 dock_status dock_create_pocket_from_receptor(const dock_grid *grid, const dock_forcefield *ff,
                                              int32_t n_atoms, const float *xyz, const int32_t *type,
-                                             const float *charge, int32_t device, dock_pocket **out);
+                                             const float *charge, int32_t layout, int32_t device,
+                                             dock_pocket **out);
+
+/* The DOCK_LAYOUT_* (never AUTO) the pocket's scoring kernel reads. */
+dock_status dock_pocket_layout(const dock_pocket *pocket, int32_t *layout);
 
 /* Copy the pocket's maps (layout above) into maps_out: a device pointer of
  * (n_types+2)*nx*ny*nz floats.  Enqueued on stream. */
@@ -119,16 +135,16 @@ typedef struct {
   const float *xyz;             /* [n_atoms][3] reference conformation */
   const int32_t *type;          /* [n_atoms] in [0, n_types) */
   const float *charge;          /* [n_atoms] */
-  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree (rings: DOCK_E_UNSUPPORTED) */
+  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree (a ring makes it DOCK_E_INVALID) */
   const int32_t *torsion_bonds; /* [n_torsions] distinct indices into bonds, neither end of degree 1 */
 } dock_ligand_desc;
 
 /* Preprocess a ligand set for a pocket: root at atom 0, ligand origin at the
  * centroid of the reference conformation, intra pairs = atom pairs at least four
  * bonds apart that lie in different rigid fragments (Algorithm 2's pair loop; no
- * distance cutoff).  Errors: DOCK_E_INVALID (bad tree, torsion on a terminal or
- * repeated bond, type out of range, n_ligands < 1), DOCK_E_UNSUPPORTED (> 96
- * atoms, > 32 torsions, bond graph with a cycle), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+ * distance cutoff).  Errors: DOCK_E_INVALID (bonds not a tree, torsion on a
+ * terminal or repeated bond, type out of range, non-finite input, n_ligands < 1),
+ * DOCK_E_UNSUPPORTED (> 96 atoms, > 32 torsions), DOCK_E_NOMEM, DOCK_E_DEVICE. */
 dock_status dock_create_ligands(const dock_pocket *pocket, const dock_ligand_desc *ligands,
                                 int32_t n_ligands, dock_ligands **out);
 
@@ -196,6 +212,27 @@ dock_status dock_de_trials(const dock_ligands *ligs, const dock_search_params *p
 dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, const dock_search_params *params,
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);
+
+/* ---- Roofline probes: measurement aids, not steps of the docking path. ---- */
+
+/* Map lookups alone, as the inter-energy loop of Algorithm 2 performs them: each
+ * of n_lanes lanes interpolates per_lane atoms placed uniformly at random in the
+ * box [box_lo, box_hi] (host float[3] each), with random types and charges,
+ * through the pocket's device layout and the scoring kernel's gather code, and
+ * writes the sum of its values to out[lane] (device float[n_lanes]).  Timing it
+ * gives the measured rate of random lookups at this map footprint.  Errors:
+ * DOCK_E_INVALID (null pointers, empty box, n_lanes outside 1..2^31, per_lane
+ * not a positive multiple of 4), DOCK_E_DEVICE. */
+dock_status dock_gather_probe(const dock_pocket *pocket, const float box_lo[3], const float box_hi[3],
+                              int64_t n_lanes, int32_t per_lane, uint64_t seed, float *out, void *stream);
+
+/* Intra-energy pair terms alone (Algorithm 2's pair loop body) on register
+ * coordinates: n_lanes lanes evaluate per_lane 12-6 pair terms each with the
+ * pocket's force-field constants and write their sums to out[lane] (device
+ * float[n_lanes]).  Timing it gives the measured VALU rate of pair terms.
+ * Errors as dock_gather_probe. */
+dock_status dock_pair_probe(const dock_pocket *pocket, int64_t n_lanes, int32_t per_lane, float *out,
+                            void *stream);
 
 #ifdef __cplusplus
 }

@@ -7,12 +7,13 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdock.so")
-SOURCES = ["api.hip", "score.hip", "search.hip", "maps.hip"]
+SOURCES = ["api.hip", "score.hip", "search.hip", "maps.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-Wall", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-result", "-I" + INCLUDE,
     # packed FP32 instructions are kept out of every code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

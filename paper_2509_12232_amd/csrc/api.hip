@@ -9,7 +9,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/dock.h"
+#include "dock.h"
 #include "dock_internal.h"
 
 using namespace dock;
@@ -75,15 +75,69 @@ struct dock_pocket {
   std::vector<float> Rii, epsii, vol, solpar;
   std::vector<uint8_t> hbond;
   float coulomb = 0, qsolpar = 0;
-  float *maps = nullptr;
+  float *maps = nullptr;      // ABI layout
   int64_t plane = 0;
+  int32_t layout = kLinear;    // layout the scoring kernel reads
+  void *tpack = nullptr;       // packed type maps
+  float4 *edpack = nullptr;    // packed electrostatic/desolvation records
+  int64_t t_stride = 0;
+  MapData view() const {
+    MapData m{};
+    m.lin = maps;
+    m.t_stride = t_stride;
+    if (layout == kZPair) m.tz = (const float2 *)tpack, m.edz = edpack;
+    if (layout == kYZQuad) m.tq = (const float4 *)tpack, m.edq = edpack;
+    return m;
+  }
 };
+
+// Packed layout for the scoring kernel: the yz-quad layout (4x the type maps,
+// the fewest cache lines per lookup) while its copy stays within kQuadBudget
+// bytes, so that it remains resident in the 256 MB Infinity Cache; else the
+// z-pair layout (2x).
+static constexpr double kQuadBudget = 240.0 * 1024 * 1024;
+
+static int32_t choose_layout(const MapGeom &g, int32_t requested) {
+  if (requested != DOCK_LAYOUT_AUTO) return requested;
+  const double el = (double)g.nx * (g.ny - 1) * (g.nz - 1);
+  const double quad_bytes = el * 16.0 * g.n_types + el * 32.0;
+  return quad_bytes <= kQuadBudget ? kYZQuad : kZPair;
+}
+
+static bool valid_layout(int32_t layout) {
+  return layout == DOCK_LAYOUT_AUTO || layout == DOCK_LAYOUT_LINEAR || layout == DOCK_LAYOUT_ZPAIR ||
+         layout == DOCK_LAYOUT_YZQUAD;
+}
+
+// Builds the packed copy of p->maps (already on the device).
+static hipError_t pack_maps(dock_pocket *p, int32_t requested) {
+  p->layout = choose_layout(p->geom, requested);
+  if (p->layout != kZPair && p->layout != kYZQuad) return hipSuccess;  // kLinear reads p->maps directly
+  const MapGeom &g = p->geom;
+  const int py = p->layout == kYZQuad ? g.ny - 1 : g.ny;
+  const int64_t n_el = (int64_t)g.nx * py * (g.nz - 1);
+  const size_t tbytes = (size_t)n_el * g.n_types * (p->layout == kYZQuad ? 16 : 8);
+  const size_t edbytes = (size_t)n_el * (p->layout == kYZQuad ? 32 : 16);
+  p->t_stride = n_el;
+  hipError_t e = hipMalloc(&p->tpack, tbytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->edpack, edbytes);
+  if (e == hipSuccess) e = launch_relayout(g, p->layout, p->maps, p->tpack, p->edpack, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  return e;
+}
+
+static void free_pocket(dock_pocket *p) {
+  for (void *q : {(void *)p->maps, p->tpack, (void *)p->edpack})
+    if (q) (void)hipFree(q);
+  delete p;
+}
 
 struct dock_ligands {
   int device = 0;
   int n_ligs = 0;
   int max_atoms = 0, max_tors = 0;
   std::vector<LigHeader> hdr_host;
+  std::vector<int32_t> pair_count;
   LigHeader *hdr = nullptr;
   float4 *atoms = nullptr;
   int32_t *atom_type = nullptr;
@@ -157,9 +211,11 @@ static void fill_geom(dock_pocket *p, const dock_grid *g) {
 }
 
 extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t maps_on_device,
-                                          const dock_forcefield *ff, int32_t device, dock_pocket **out) {
+                                          const dock_forcefield *ff, int32_t layout, int32_t device,
+                                          dock_pocket **out) {
   if (!out) return set_err(DOCK_E_INVALID, "null out");
   *out = nullptr;
+  if (!valid_layout(layout)) return set_err(DOCK_E_INVALID, "unknown layout %d", layout);
   dock_status st = check_ff(ff);
   if (st) return st;
   if ((st = check_grid(grid, ff->n_types))) return st;
@@ -174,9 +230,9 @@ extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *ma
   hipError_t e = hipMalloc((void **)&p->maps, bytes);
   if (e == hipSuccess)
     e = hipMemcpy(p->maps, maps, bytes, maps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = pack_maps(p, layout);
   if (e != hipSuccess) {
-    if (p->maps) (void)hipFree(p->maps);
-    delete p;
+    free_pocket(p);
     return hip_err(e, "pocket maps");
   }
   *out = p;
@@ -185,9 +241,11 @@ extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *ma
 
 extern "C" dock_status dock_create_pocket_from_receptor(const dock_grid *grid, const dock_forcefield *ff,
                                                         int32_t n_atoms, const float *xyz, const int32_t *type,
-                                                        const float *charge, int32_t device, dock_pocket **out) {
+                                                        const float *charge, int32_t layout, int32_t device,
+                                                        dock_pocket **out) {
   if (!out) return set_err(DOCK_E_INVALID, "null out");
   *out = nullptr;
+  if (!valid_layout(layout)) return set_err(DOCK_E_INVALID, "unknown layout %d", layout);
   dock_status st = check_ff(ff);
   if (st) return st;
   if ((st = check_grid(grid, ff->n_types))) return st;
@@ -249,12 +307,12 @@ extern "C" dock_status dock_create_pocket_from_receptor(const dock_grid *grid, c
     m.maps = p->maps;
     e = launch_build_maps(m, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = pack_maps(p, layout);
   }
   for (void *q : {(void *)d_rec, (void *)d_rt, (void *)d_A, (void *)d_B, (void *)d_hb, (void *)d_sol, (void *)d_vol})
     if (q) (void)hipFree(q);
   if (e != hipSuccess) {
-    if (p->maps) (void)hipFree(p->maps);
-    delete p;
+    free_pocket(p);
     return hip_err(e, "map build");
   }
   *out = p;
@@ -271,11 +329,16 @@ extern "C" dock_status dock_pocket_maps(const dock_pocket *p, float *maps_out, v
   return DOCK_OK;
 }
 
+extern "C" dock_status dock_pocket_layout(const dock_pocket *p, int32_t *layout) {
+  if (!p || !layout) return set_err(DOCK_E_INVALID, "null argument");
+  *layout = p->layout;
+  return DOCK_OK;
+}
+
 extern "C" dock_status dock_destroy_pocket(dock_pocket *p) {
   if (!p) return DOCK_OK;
   DeviceScope ds(p->device);
-  if (p->maps) (void)hipFree(p->maps);
-  delete p;
+  free_pocket(p);
   return DOCK_OK;
 }
 
@@ -286,8 +349,8 @@ struct PrepOut {
   std::vector<float4> atoms;
   std::vector<int32_t> types;
   std::vector<TorRec> tors;
-  std::vector<PairRec> pairs;  // 12-6 pairs, then 12-10 pairs
-  int n_hb = 0;
+  std::vector<PairRec> pairs;  // 12-6 groups, two spare zero groups, then 12-10 pairs
+  int n_plain = 0, n_hb = 0, n_groups = 0;
 };
 
 // Root at atom 0; depth-first pre-order renumbering so each rotatable bond's far
@@ -403,20 +466,27 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
       const double Su = (double)P->solpar[tu] + (double)P->qsolpar * fabs(qu);
       const double Sv = (double)P->solpar[tv] + (double)P->qsolpar * fabs(qv);
       PairRec r{};
-      r.i = std::min(pos[u], pos[v]);
-      r.j = std::max(pos[u], pos[v]);
+      r.ij = std::min(pos[u], pos[v]) | (std::max(pos[u], pos[v]) << 16);
       r.A = (float)A;
       r.B = (float)B;
       r.qq = (float)((double)P->coulomb * qu * qv);
       r.sv = (float)(Su * P->vol[tv] + Sv * P->vol[tu]);
       (h ? hb : plain).push_back(r);
     }
-  auto by_ij = [](const PairRec &x, const PairRec &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; };
+  // sort by (i, j); ij packs i in the low half, so compare the halves explicitly
+  auto by_ij = [](const PairRec &x, const PairRec &y) {
+    const int xi = x.ij & 0xffff, yi = y.ij & 0xffff;
+    return xi != yi ? xi < yi : (x.ij >> 16) < (y.ij >> 16);
+  };
   std::sort(plain.begin(), plain.end(), by_ij);
   std::sort(hb.begin(), hb.end(), by_ij);
-  o.pairs = plain;
-  o.pairs.insert(o.pairs.end(), hb.begin(), hb.end());
+  o.n_plain = (int)plain.size();
   o.n_hb = (int)hb.size();
+  o.n_groups = (o.n_plain + 3) / 4;
+  // 12-6 pairs padded to whole groups of four, two spare all-zero groups, then 12-10 pairs
+  o.pairs = plain;
+  o.pairs.resize((size_t)4 * (o.n_groups + 2), PairRec{0, 0.f, 0.f, 0.f, 0.f});
+  o.pairs.insert(o.pairs.end(), hb.begin(), hb.end());
   return DOCK_OK;
 }
 
@@ -435,6 +505,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   if (!pocket || !ligands) return set_err(DOCK_E_INVALID, "null argument");
   if (n_ligands < 1) return set_err(DOCK_E_INVALID, "n_ligands must be >= 1");
   std::vector<LigHeader> hdr(n_ligands);
+  std::vector<int32_t> pair_count(n_ligands);
   std::vector<float4> atoms;
   std::vector<int32_t> types;
   std::vector<TorRec> tors;
@@ -447,12 +518,13 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
     LigHeader &h = hdr[l];
     h.n_atoms = (int)o.atoms.size();
     h.n_tors = (int)o.tors.size();
-    h.n_pairs = (int)o.pairs.size() - o.n_hb;
+    h.n_groups = o.n_groups;
     h.n_pairs_hb = o.n_hb;
     h.atom_off = (int)atoms.size();
     h.tor_off = (int)tors.size();
     h.pair_off = (int)pairs.size();
-    h.pad = 0;
+    h.hb_off = h.pair_off + 4 * (o.n_groups + 2);
+    pair_count[l] = o.n_plain + o.n_hb;
     if ((double)pairs.size() + o.pairs.size() > 2.0e9) return set_err(DOCK_E_UNSUPPORTED, "ligand set too large");
     atoms.insert(atoms.end(), o.atoms.begin(), o.atoms.end());
     types.insert(types.end(), o.types.begin(), o.types.end());
@@ -469,6 +541,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   L->max_atoms = max_atoms;
   L->max_tors = max_tors;
   L->hdr_host = hdr;
+  L->pair_count = pair_count;
   hipError_t e = upload(&L->hdr, hdr);
   if (e == hipSuccess) e = upload(&L->atoms, atoms);
   if (e == hipSuccess) e = upload(&L->atom_type, types);
@@ -485,7 +558,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
 extern "C" dock_status dock_ligand_pair_count(const dock_ligands *L, int32_t lig, int32_t *n_pairs) {
   if (!L || !n_pairs) return set_err(DOCK_E_INVALID, "null argument");
   if (lig < 0 || lig >= L->n_ligs) return set_err(DOCK_E_INVALID, "ligand index out of range");
-  *n_pairs = L->hdr_host[lig].n_pairs + L->hdr_host[lig].n_pairs_hb;
+  *n_pairs = L->pair_count[lig];
   return DOCK_OK;
 }
 
@@ -502,7 +575,8 @@ static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
   a.L = L->view();
   a.geom = p->geom;
   a.ff = p->ffc;
-  a.maps = p->maps;
+  a.maps = p->view();
+  a.layout = p->layout;
   a.lds_atoms = L->max_atoms;
   return a;
 }
@@ -636,5 +710,37 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
     if (e != hipSuccess) return hip_err(e, "search loop");
   }
   HIP_TRY(launch_de_best(nl, P, g_stride, population, pop_energy, best_genotypes, best_energies, s), "best");
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ probes
+extern "C" dock_status dock_gather_probe(const dock_pocket *p, const float box_lo[3], const float box_hi[3],
+                                         int64_t n_lanes, int32_t per_lane, uint64_t seed, float *out,
+                                         void *stream) {
+  if (!p || !box_lo || !box_hi || !out) return set_err(DOCK_E_INVALID, "null argument");
+  if (n_lanes < 1 || n_lanes > ((int64_t)1 << 31) || per_lane < 4 || per_lane % 4)
+    return set_err(DOCK_E_INVALID, "n_lanes in 1..2^31, per_lane a positive multiple of 4");
+  ProbeBox box{};
+  for (int d = 0; d < 3; ++d) {
+    if (!(box_lo[d] <= box_hi[d])) return set_err(DOCK_E_INVALID, "empty probe box");
+    box.lo[d] = box_lo[d];
+    box.ext[d] = box_hi[d] - box_lo[d];
+  }
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(launch_gather_probe(p->geom, p->view(), p->layout, box, n_lanes, per_lane, (uint32_t)seed, out,
+                              (hipStream_t)stream),
+          "gather probe launch");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_pair_probe(const dock_pocket *p, int64_t n_lanes, int32_t per_lane, float *out,
+                                       void *stream) {
+  if (!p || !out) return set_err(DOCK_E_INVALID, "null argument");
+  if (n_lanes < 1 || n_lanes > ((int64_t)1 << 31) || per_lane < 4 || per_lane % 4)
+    return set_err(DOCK_E_INVALID, "n_lanes in 1..2^31, per_lane a positive multiple of 4");
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(launch_pair_probe(p->ffc, n_lanes, per_lane, out, (hipStream_t)stream), "pair probe launch");
   return DOCK_OK;
 }

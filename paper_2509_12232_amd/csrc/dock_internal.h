@@ -14,15 +14,18 @@ constexpr int kWave = 64;
 
 // Per ligand.  Atoms are renumbered in depth-first pre-order from the root
 // (atom 0), so every rotatable bond's moving fragment is one contiguous range.
+// Pairs: the 12-6 pairs in groups of four (the last group padded with records
+// whose coefficients are all zero, which contribute exactly 0), two further
+// all-zero groups that the kernel may prefetch past the end, then the 12-10 pairs.
 struct alignas(32) LigHeader {
   int32_t n_atoms;
   int32_t n_tors;
-  int32_t n_pairs;     // 12-6 pairs first ...
-  int32_t n_pairs_hb;  // ... then 12-10 pairs
+  int32_t n_groups;    // groups of four 12-6 pair records
+  int32_t n_pairs_hb;  // 12-10 pairs, starting at hb_off
   int32_t atom_off;    // into atoms[] / atom_type[]
   int32_t tor_off;     // into tors[]
   int32_t pair_off;    // into pairs[]
-  int32_t pad;
+  int32_t hb_off;      // into pairs[]
 };
 
 // Rotatable bond: axis from atom a (root side) to atom lo (the far atom, first of
@@ -32,18 +35,39 @@ struct alignas(16) TorRec {
   int32_t a, lo, hi, gene;
 };
 
-// Non-bonded pair with its precomputed coefficients.
-struct alignas(32) PairRec {
-  int32_t i, j;
+// Non-bonded pair with its precomputed coefficients (20 bytes, so the pair table
+// of a typical ligand fits the scalar data cache).
+struct PairRec {
+  int32_t ij;    // i | j << 16
   float A, B;    // repulsive / attractive coefficients of the 12-6 or 12-10 term
   float qq;      // coulomb * q_i * q_j
   float sv;      // S_i vol_j + S_j vol_i
-  int32_t pad0, pad1;
 };
+static_assert(sizeof(PairRec) == 20, "PairRec is five dwords");
 
 struct MapGeom {
   int32_t nx, ny, nz, n_types;
   float ox, oy, oz, inv_h;
+};
+
+// Device layouts of the maps used by the scoring kernel.  The ABI layout is
+// kept as is (kLinear); the packed layouts duplicate neighbouring nodes so that
+// the eight corners of a cell come from fewer cache lines:
+//   kZPair:  per type, float2 (M[x,y,z], M[x,y,z+1]) over z < nz-1; the x and
+//            x+1 elements of a row are adjacent (16 B), so a cell needs two rows.
+//            Electrostatic + desolvation as float4 (E, E_z+1, D, D_z+1).
+//   kYZQuad: per type, float4 (M[x,y,z], M[x,y+1,z], M[x,y,z+1], M[x,y+1,z+1])
+//            over y < ny-1, z < nz-1; a cell is the two adjacent elements x, x+1
+//            (32 B).  Electrostatic + desolvation as two float4 quads per node.
+enum MapLayout : int32_t { kLinear = 0, kZPair = 1, kYZQuad = 2 };
+
+struct MapData {
+  const float *lin;      // [n_types+2][nz][ny][nx]
+  const float2 *tz;      // kZPair types:  [n_types][nz-1][ny][nx]
+  const float4 *edz;     // kZPair E/D:    [nz-1][ny][nx]
+  const float4 *tq;      // kYZQuad types: [n_types][nz-1][ny-1][nx]
+  const float4 *edq;     // kYZQuad E/D:   [nz-1][ny-1][nx][2]
+  int64_t t_stride;      // elements per type map in the packed layout
 };
 
 struct FFConst {
@@ -67,7 +91,8 @@ struct ScoreLaunch {
   LigandsDev L;
   MapGeom geom;
   FFConst ff;
-  const float *maps;
+  MapData maps;
+  int32_t layout;
   const int32_t *pose_ligand;  // may be null
   int32_t poses_per_ligand;    // > 0: ligand = pose / poses_per_ligand (pose_ligand ignored)
   const float *genotypes;
@@ -113,5 +138,22 @@ struct MapBuild {
 };
 
 hipError_t launch_build_maps(const MapBuild &m, hipStream_t s);
+
+// Derive a packed layout from the linear maps (buffers sized by the caller).
+hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, void *types_out, float4 *ed_out,
+                           hipStream_t s);
+
+}  // namespace dock
+
+namespace dock {
+
+// Box for the gather probe's positions.
+struct ProbeBox {
+  float lo[3], ext[3];
+};
+
+hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const ProbeBox &box,
+                               int64_t n_lanes, int32_t per_lane, uint32_t seed, float *out, hipStream_t s);
+hipError_t launch_pair_probe(const FFConst &F, int64_t n_lanes, int32_t per_lane, float *out, hipStream_t s);
 
 }  // namespace dock

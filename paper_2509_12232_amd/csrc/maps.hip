@@ -77,3 +77,43 @@ hipError_t launch_build_maps(const MapBuild &m, hipStream_t s) {
 }
 
 }  // namespace dock
+
+namespace dock {
+
+// One thread per element of the packed grid; every type map plus the E/D record.
+__global__ void relayout_kernel(MapGeom g, int32_t layout, const float *__restrict__ lin, void *types_out,
+                                float4 *__restrict__ ed_out) {
+  if (layout != kZPair && layout != kYZQuad) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int py = layout == kYZQuad ? ny - 1 : ny;
+  const int64_t n_el = (int64_t)nx * py * (nz - 1);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_el) return;
+  const int x = (int)(e % nx), y = (int)((e / nx) % py), z = (int)(e / ((int64_t)nx * py));
+  const int64_t plane = (int64_t)nx * ny * nz;
+  auto at = [&](int m, int xx, int yy, int zz) { return lin[m * plane + ((int64_t)zz * ny + yy) * nx + xx]; };
+  const int E = g.n_types, D = g.n_types + 1;
+  if (layout == kZPair) {
+    float2 *T = (float2 *)types_out;
+    for (int t = 0; t < g.n_types; ++t) T[t * n_el + e] = make_float2(at(t, x, y, z), at(t, x, y, z + 1));
+    ed_out[e] = make_float4(at(E, x, y, z), at(E, x, y, z + 1), at(D, x, y, z), at(D, x, y, z + 1));
+  } else {
+    float4 *T = (float4 *)types_out;
+    for (int t = 0; t < g.n_types; ++t)
+      T[t * n_el + e] = make_float4(at(t, x, y, z), at(t, x, y + 1, z), at(t, x, y, z + 1), at(t, x, y + 1, z + 1));
+    ed_out[2 * e] = make_float4(at(E, x, y, z), at(E, x, y + 1, z), at(E, x, y, z + 1), at(E, x, y + 1, z + 1));
+    ed_out[2 * e + 1] = make_float4(at(D, x, y, z), at(D, x, y + 1, z), at(D, x, y, z + 1), at(D, x, y + 1, z + 1));
+  }
+}
+
+hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, void *types_out, float4 *ed_out,
+                           hipStream_t s) {
+  if (layout != kZPair && layout != kYZQuad) return hipErrorInvalidValue;
+  const int py = layout == kYZQuad ? g.ny - 1 : g.ny;
+  const int64_t n_el = (int64_t)g.nx * py * (g.nz - 1);
+  hipLaunchKernelGGL(relayout_kernel, dim3((unsigned)((n_el + 255) / 256)), dim3(256), 0, s, g, layout, lin,
+                     types_out, ed_out);
+  return hipGetLastError();
+}
+
+}  // namespace dock

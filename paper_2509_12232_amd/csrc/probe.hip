@@ -1,0 +1,99 @@
+// probe.hip -- roofline probes for the scoring kernel's two halves.
+//
+// gather_probe: the inter-energy lookups alone (Algorithm 2's map lookups):
+// each lane interpolates atoms at positions drawn uniformly in a box, with
+// uniform types and charges, through the same layout and gather code as the
+// scoring kernel, at full occupancy and with no other work.  Its rate is the
+// measured ceiling for random map lookups at this map footprint.
+//
+// pair_probe: the intra-energy pair term alone on register-resident
+// coordinates, at full occupancy: the measured VALU ceiling for pair terms.
+#include "dock_internal.h"
+#include "score_pose.h"
+
+namespace dock {
+
+// Counter-based hash (a 32-bit finaliser) for probe positions; no statistical
+// requirement beyond spreading the lookups over the box.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ float unit01(uint32_t h) { return (float)(h >> 8) * (1.0f / 16777216.0f); }
+
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M, ProbeBox box, int per_lane,
+                                                            uint32_t seed, int64_t n_lanes, float *out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)t >= n_lanes) return;
+  float acc = 0.f;
+  constexpr int U = 4;  // lookups in flight per lane
+  for (int m = 0; m < per_lane; m += U) {
+    Corners<LAYOUT> c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t h = mix32(seed ^ mix32(t * 0x9E3779B9u + (uint32_t)(m + u)));
+      const float px = box.lo[0] + box.ext[0] * unit01(mix32(h + 1));
+      const float py = box.lo[1] + box.ext[1] * unit01(mix32(h + 2));
+      const float pz = box.lo[2] + box.ext[2] * unit01(mix32(h + 3));
+      const int type = (int)(h % (uint32_t)G.n_types);
+      const float q = unit01(h) - 0.5f;
+      c[u] = gather_corners<LAYOUT>(G, M, type, q, px, py, pz);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += interpolate_corners<LAYOUT>(c[u]);
+  }
+  out[t] = acc;
+}
+
+hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const ProbeBox &box,
+                               int64_t n_lanes, int32_t per_lane, uint32_t seed, float *out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n_lanes + 255) / 256);
+  switch (layout) {
+    case kLinear:
+      hipLaunchKernelGGL(gather_probe_kernel<kLinear>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      break;
+    case kZPair:
+      hipLaunchKernelGGL(gather_probe_kernel<kZPair>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      break;
+    case kYZQuad:
+      hipLaunchKernelGGL(gather_probe_kernel<kYZQuad>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Pair terms on coordinates held in registers: each lane evaluates per_lane pair
+// terms with synthetic coordinates and coefficients.
+__global__ __launch_bounds__(256) void pair_probe_kernel(FFConst F, int per_lane, int64_t n_lanes, float *out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)t >= n_lanes) return;
+  const uint32_t h = mix32(t);
+  float x = 3.f * unit01(h), y = 3.f * unit01(mix32(h + 1)), z = 3.f * unit01(mix32(h + 2));
+  PairRec P{0, 1.2e5f, 0.9f, -30.f, 0.002f};
+  float acc = 0.f;
+  constexpr int U = 4;
+  for (int m = 0; m < per_lane; m += U) {
+    float e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) e[u] = pair_term<false>(F, P, x + 0.5f * u, y - 0.25f * u, z + (float)m * 1e-6f);
+    acc += (e[0] + e[1]) + (e[2] + e[3]);
+    x += 1e-3f;
+  }
+  out[t] = acc;
+}
+
+hipError_t launch_pair_probe(const FFConst &F, int64_t n_lanes, int32_t per_lane, float *out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n_lanes + 255) / 256);
+  hipLaunchKernelGGL(pair_probe_kernel, dim3(blocks), dim3(256), 0, s, F, per_lane, n_lanes, out);
+  return hipGetLastError();
+}
+
+}  // namespace dock

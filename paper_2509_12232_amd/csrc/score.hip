@@ -8,6 +8,7 @@
 
 namespace dock {
 
+template <int LAYOUT>
 __global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
@@ -25,22 +26,33 @@ __global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
     const LigHeader H = A.L.hdr[cur];
-    if (valid && lig == cur) e = score_pose<kWave>(A.L, A.geom, A.ff, A.maps, H, g, my);
+    if (valid && lig == cur) e = score_pose<kWave, LAYOUT>(A.L, A.geom, A.ff, A.maps, H, g, my);
     todo &= ~__ballot(valid && lig == cur);
   }
   A.energies[pose] = e;
 }
 
-hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
-  if (a.n_poses <= 0) return hipSuccess;
+template <int LAYOUT>
+static hipError_t launch_score_t(const ScoreLaunch &a, hipStream_t s) {
   const int64_t blocks = (a.n_poses + kWave - 1) / kWave;
   const size_t lds = (size_t)a.lds_atoms * 3 * kWave * sizeof(float);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)score_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)score_kernel<LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(score_kernel, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
+  hipLaunchKernelGGL(score_kernel<LAYOUT>, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
+  if (a.n_poses <= 0) return hipSuccess;
+  switch (a.layout) {
+    case kLinear: return launch_score_t<kLinear>(a, s);
+    case kZPair: return launch_score_t<kZPair>(a, s);
+    case kYZQuad: return launch_score_t<kYZQuad>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dock

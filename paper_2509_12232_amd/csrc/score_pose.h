@@ -14,39 +14,122 @@ namespace dock {
 
 __device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-// Trilinear interpolation of (T_type + q E + |q| D) at one atom; 0 outside the
-// closed grid box (Algorithm 2's "nearby" test).
-__device__ __forceinline__ float atom_inter(const MapGeom &G, const float *__restrict__ maps, int type,
-                                            float q, float px, float py, float pz) {
+// How many pair slices ahead of its use an atom's map loads are issued.
+constexpr int kGatherAhead = 1;
+
+// Raw map values of one atom's grid cell, as loaded for the layout, plus what
+// is needed to finish the interpolation later.  v[b] of the combined value is
+// corner (x + (b&1), y + (b>>1 & 1), z + (b>>2 & 1)).
+template <int LAYOUT>
+struct Corners;
+
+template <>
+struct Corners<kLinear> {
+  float t[8], e[8], d[8];
+  float fx, fy, fz, q, aq;
+  bool inside;
+  __device__ __forceinline__ void combine(float v[8]) const {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v[b] = fmaf(aq, d[b], fmaf(q, e[b], t[b]));
+  }
+};
+
+template <>
+struct Corners<kZPair> {
+  float2 t00, t10, t01, t11;   // (z, z+1) at x/x+1, y/y+1
+  float4 d00, d10, d01, d11;   // (E z, E z+1, D z, D z+1)
+  float fx, fy, fz, q, aq;
+  bool inside;
+  __device__ __forceinline__ void combine(float v[8]) const {
+    v[0] = fmaf(aq, d00.z, fmaf(q, d00.x, t00.x));
+    v[1] = fmaf(aq, d10.z, fmaf(q, d10.x, t10.x));
+    v[2] = fmaf(aq, d01.z, fmaf(q, d01.x, t01.x));
+    v[3] = fmaf(aq, d11.z, fmaf(q, d11.x, t11.x));
+    v[4] = fmaf(aq, d00.w, fmaf(q, d00.y, t00.y));
+    v[5] = fmaf(aq, d10.w, fmaf(q, d10.y, t10.y));
+    v[6] = fmaf(aq, d01.w, fmaf(q, d01.y, t01.y));
+    v[7] = fmaf(aq, d11.w, fmaf(q, d11.y, t11.y));
+  }
+};
+
+template <>
+struct Corners<kYZQuad> {
+  float4 t0, t1, e0, d0, e1, d1;   // quads (y z, y+1 z, y z+1, y+1 z+1) at x and x+1
+  float fx, fy, fz, q, aq;
+  bool inside;
+  __device__ __forceinline__ void combine(float v[8]) const {
+    v[0] = fmaf(aq, d0.x, fmaf(q, e0.x, t0.x));
+    v[1] = fmaf(aq, d1.x, fmaf(q, e1.x, t1.x));
+    v[2] = fmaf(aq, d0.y, fmaf(q, e0.y, t0.y));
+    v[3] = fmaf(aq, d1.y, fmaf(q, e1.y, t1.y));
+    v[4] = fmaf(aq, d0.z, fmaf(q, e0.z, t0.z));
+    v[5] = fmaf(aq, d1.z, fmaf(q, e1.z, t1.z));
+    v[6] = fmaf(aq, d0.w, fmaf(q, e0.w, t0.w));
+    v[7] = fmaf(aq, d1.w, fmaf(q, e1.w, t1.w));
+  }
+};
+
+// Trilinear interpolation of (T_type + q E + |q| D) from loaded corners; 0 outside
+// the closed grid box (Algorithm 2's "nearby" test).
+template <int LAYOUT>
+__device__ __forceinline__ float interpolate_corners(const Corners<LAYOUT> &C) {
+  float v[8];
+  C.combine(v);
+  const float c00 = lerp1(v[0], v[1], C.fx), c10 = lerp1(v[2], v[3], C.fx);
+  const float c01 = lerp1(v[4], v[5], C.fx), c11 = lerp1(v[6], v[7], C.fx);
+  const float c0 = lerp1(c00, c10, C.fy), c1 = lerp1(c01, c11, C.fy);
+  const float e = lerp1(c0, c1, C.fz);
+  return C.inside ? e : 0.f;
+}
+
+// Cell of an atom at p and the loads of its corner values.
+template <int LAYOUT>
+__device__ __forceinline__ Corners<LAYOUT> gather_corners(const MapGeom &G, const MapData &M, int type, float q,
+                                                          float px, float py, float pz) {
+  Corners<LAYOUT> C;
   const float ux = (px - G.ox) * G.inv_h;
   const float uy = (py - G.oy) * G.inv_h;
   const float uz = (pz - G.oz) * G.inv_h;
   const float mx = (float)(G.nx - 1), my = (float)(G.ny - 1), mz = (float)(G.nz - 1);
-  const bool inside = (ux >= 0.f) & (ux <= mx) & (uy >= 0.f) & (uy <= my) & (uz >= 0.f) & (uz <= mz);
+  C.inside = (ux >= 0.f) & (ux <= mx) & (uy >= 0.f) & (uy <= my) & (uz >= 0.f) & (uz <= mz);
   // cell index clamped into [0, n-2] so that every load stays in bounds, also
   // for atoms outside the box (whose contribution is then discarded)
   const float fcx = fminf(fmaxf(floorf(ux), 0.f), mx - 1.f);
   const float fcy = fminf(fmaxf(floorf(uy), 0.f), my - 1.f);
   const float fcz = fminf(fmaxf(floorf(uz), 0.f), mz - 1.f);
-  const float fx = ux - fcx, fy = uy - fcy, fz = uz - fcz;
-  const int nx = G.nx, nxy = G.nx * G.ny;
-  const int plane = nxy * G.nz;
-  const int idx = (int)fcx + nx * (int)fcy + nxy * (int)fcz;
-  const float *T = maps + (size_t)type * plane;
-  const float *E = maps + (size_t)G.n_types * plane;
-  const float *D = E + plane;
-  const float aq = fabsf(q);
-  float v[8];
+  C.fx = ux - fcx;
+  C.fy = uy - fcy;
+  C.fz = uz - fcz;
+  C.q = q;
+  C.aq = fabsf(q);
+  const int cx = (int)fcx, cy = (int)fcy, cz = (int)fcz;
+  const int nx = G.nx;
+  if constexpr (LAYOUT == kLinear) {
+    const int nxy = G.nx * G.ny;
+    const int plane = nxy * G.nz;
+    const int idx = cx + nx * cy + nxy * cz;
+    const float *T = M.lin + (size_t)type * plane;
+    const float *E = M.lin + (size_t)G.n_types * plane;
+    const float *D = E + plane;
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int o = idx + (b & 1) + ((b >> 1) & 1) * nx + ((b >> 2) & 1) * nxy;
-    v[b] = fmaf(aq, D[o], fmaf(q, E[o], T[o]));
+    for (int b = 0; b < 8; ++b) {
+      const int o = idx + (b & 1) + ((b >> 1) & 1) * nx + ((b >> 2) & 1) * nxy;
+      C.t[b] = T[o];
+      C.e[b] = E[o];
+      C.d[b] = D[o];
+    }
+  } else if constexpr (LAYOUT == kZPair) {
+    const int e = cx + nx * (cy + G.ny * cz);
+    const float2 *T = M.tz + (size_t)type * M.t_stride;
+    C.t00 = T[e]; C.t10 = T[e + 1]; C.t01 = T[e + nx]; C.t11 = T[e + nx + 1];
+    C.d00 = M.edz[e]; C.d10 = M.edz[e + 1]; C.d01 = M.edz[e + nx]; C.d11 = M.edz[e + nx + 1];
+  } else {
+    const int e = cx + nx * (cy + (G.ny - 1) * cz);
+    const float4 *T = M.tq + (size_t)type * M.t_stride;
+    C.t0 = T[e]; C.t1 = T[e + 1];
+    C.e0 = M.edq[2 * e]; C.d0 = M.edq[2 * e + 1]; C.e1 = M.edq[2 * e + 2]; C.d1 = M.edq[2 * e + 3];
   }
-  const float c00 = lerp1(v[0], v[1], fx), c10 = lerp1(v[2], v[3], fx);
-  const float c01 = lerp1(v[4], v[5], fx), c11 = lerp1(v[6], v[7], fx);
-  const float c0 = lerp1(c00, c10, fy), c1 = lerp1(c01, c11, fy);
-  const float e = lerp1(c0, c1, fz);
-  return inside ? e : 0.f;
+  return C;
 }
 
 // One non-bonded pair term.  hb selects the 12-10 attractive exponent.
@@ -73,11 +156,50 @@ __device__ __forceinline__ float &at(float *my, int atom, int c) {
   return my[(3 * atom + c) * STRIDE];
 }
 
+// Pair term of record P with both atoms' coordinates read from this lane's column.
+template <bool HB, int STRIDE>
+__device__ __forceinline__ float pair_energy(const FFConst &F, const PairRec &P, float *my) {
+  const int i = P.ij & 0xffff, j = P.ij >> 16;
+  const float dx = at<STRIDE>(my, i, 0) - at<STRIDE>(my, j, 0);
+  const float dy = at<STRIDE>(my, i, 1) - at<STRIDE>(my, j, 1);
+  const float dz = at<STRIDE>(my, i, 2) - at<STRIDE>(my, j, 2);
+  return pair_term<HB>(F, P, dx, dy, dz);
+}
+
+// Four pair records (one group), fetched with scalar loads.
+struct PairGroup {
+  PairRec r[4];
+  __device__ __forceinline__ void load(const PairRec *__restrict__ p) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = p[u];
+  }
+};
+
+// Coordinates of both atoms of each pair of a group, from this lane's column.
+template <int STRIDE>
+struct GroupCoords {
+  float xi[4], yi[4], zi[4], xj[4], yj[4], zj[4];
+  __device__ __forceinline__ void load(const PairGroup &G, float *my) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = G.r[u].ij & 0xffff, j = G.r[u].ij >> 16;
+      xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
+      xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
+    }
+  }
+  __device__ __forceinline__ float energy(const FFConst &F, const PairGroup &G) const {
+    float e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[u] = pair_term<false>(F, G.r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
+    return (e[0] + e[1]) + (e[2] + e[3]);
+  }
+};
+
 // Energy of the pose given by genotype row g (per lane) for ligand header H
 // (uniform).  Non-finite genes give NaN.
-template <int STRIDE>
-__device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F,
-                            const float *__restrict__ maps, const LigHeader &H,
+template <int STRIDE, int LAYOUT>
+__device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
+                            const LigHeader &H,
                             const float *__restrict__ g, float *__restrict__ my) {
   const int n = H.n_atoms;
   const float4 *__restrict__ atoms = L.atoms + H.atom_off;
@@ -134,37 +256,57 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   const float R10 = 2.f * (qx * qy + qw * qz), R11 = 1.f - 2.f * (qx * qx + qz * qz), R12 = 2.f * (qy * qz - qw * qx);
   const float R20 = 2.f * (qx * qz - qw * qy), R21 = 2.f * (qy * qz + qw * qx), R22 = 1.f - 2.f * (qx * qx + qy * qy);
 
-  // Algorithm 2, inter-energy loop (fused with the rigid move of each atom)
-  float inter = 0.f;
   for (int i = 0; i < n; ++i) {
     const float px = at<STRIDE>(my, i, 0), py = at<STRIDE>(my, i, 1), pz = at<STRIDE>(my, i, 2);
-    const float wx = fmaf(R00, px, fmaf(R01, py, fmaf(R02, pz, tx)));
-    const float wy = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
-    const float wz = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
-    at<STRIDE>(my, i, 0) = wx;
-    at<STRIDE>(my, i, 1) = wy;
-    at<STRIDE>(my, i, 2) = wz;
-    inter += atom_inter(G, maps, types[i], atoms[i].w, wx, wy, wz);
+    at<STRIDE>(my, i, 0) = fmaf(R00, px, fmaf(R01, py, fmaf(R02, pz, tx)));
+    at<STRIDE>(my, i, 1) = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
+    at<STRIDE>(my, i, 2) = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
   }
 
-  // Algorithm 2, intra-energy loop over the non-bonded pairs
-  float intra = 0.f;
+  // Algorithm 2: the inter-energy loop over atoms and the intra-energy loop over
+  // pairs, interleaved.  Iteration k issues the map loads of atom k+1, then
+  // evaluates the k-th of n equal slices of the pair groups, then interpolates
+  // atom k from the loads issued one iteration earlier, so the pair arithmetic
+  // covers the latency of the gathers.  Within the pair loop, the coordinates
+  // of group g+1 and the records of group g+2 are requested before group g is
+  // evaluated (the list ends with spare zero groups to read past).
   const PairRec *__restrict__ pairs = L.pairs + H.pair_off;
-#pragma unroll 4
-  for (int p = 0; p < H.n_pairs; ++p) {
-    const PairRec P = pairs[p];
-    const float dx = at<STRIDE>(my, P.i, 0) - at<STRIDE>(my, P.j, 0);
-    const float dy = at<STRIDE>(my, P.i, 1) - at<STRIDE>(my, P.j, 1);
-    const float dz = at<STRIDE>(my, P.i, 2) - at<STRIDE>(my, P.j, 2);
-    intra += pair_term<false>(F, P, dx, dy, dz);
+  const int ng = H.n_groups;
+  float inter = 0.f, intra = 0.f;
+  // ring[d] holds the loads of atom k + d; atoms are fetched kGatherAhead slices early
+  Corners<LAYOUT> ring[kGatherAhead + 1];
+#pragma unroll
+  for (int d = 0; d < kGatherAhead; ++d)
+    if (d < n)
+      ring[d] = gather_corners<LAYOUT>(G, maps, types[d], atoms[d].w, at<STRIDE>(my, d, 0), at<STRIDE>(my, d, 1),
+                                       at<STRIDE>(my, d, 2));
+  PairGroup A, B;
+  A.load(pairs);
+  B.load(pairs + 4);
+  GroupCoords<STRIDE> X;
+  X.load(A, my);
+  for (int k = 0; k < n; ++k) {
+    const int ka = k + kGatherAhead;
+    if (ka < n)
+      ring[kGatherAhead] = gather_corners<LAYOUT>(G, maps, types[ka], atoms[ka].w, at<STRIDE>(my, ka, 0),
+                                                  at<STRIDE>(my, ka, 1), at<STRIDE>(my, ka, 2));
+    const int g0 = (k * ng) / n, g1 = ((k + 1) * ng) / n;
+    for (int gi = g0; gi < g1; ++gi) {
+      GroupCoords<STRIDE> Xn;
+      Xn.load(B, my);
+      PairGroup C;
+      C.load(pairs + 4 * (gi + 2));
+      intra += X.energy(F, A);
+      A = B;
+      B = C;
+      X = Xn;
+    }
+    inter += interpolate_corners<LAYOUT>(ring[0]);
+#pragma unroll
+    for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
   }
-  for (int p = H.n_pairs; p < H.n_pairs + H.n_pairs_hb; ++p) {
-    const PairRec P = pairs[p];
-    const float dx = at<STRIDE>(my, P.i, 0) - at<STRIDE>(my, P.j, 0);
-    const float dy = at<STRIDE>(my, P.i, 1) - at<STRIDE>(my, P.j, 1);
-    const float dz = at<STRIDE>(my, P.i, 2) - at<STRIDE>(my, P.j, 2);
-    intra += pair_term<true>(F, P, dx, dy, dz);
-  }
+  const PairRec *__restrict__ hb = L.pairs + H.hb_off;
+  for (int p = 0; p < H.n_pairs_hb; ++p) intra += pair_energy<true, STRIDE>(F, hb[p], my);
   const float e = inter + intra;
   return bad ? __builtin_nanf("") : e;
 }

@@ -24,6 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 DOCK_OK, DOCK_E_INVALID, DOCK_E_NOMEM, DOCK_E_DEVICE, DOCK_E_UNSUPPORTED = range(5)
+DOCK_LAYOUT_AUTO, DOCK_LAYOUT_LINEAR, DOCK_LAYOUT_ZPAIR, DOCK_LAYOUT_YZQUAD = -1, 0, 1, 2
 _STATUS = {1: "DOCK_E_INVALID", 2: "DOCK_E_NOMEM", 3: "DOCK_E_DEVICE", 4: "DOCK_E_UNSUPPORTED"}
 
 
@@ -64,8 +65,9 @@ _P = C.c_void_p
 _lib.dock_last_error.restype = C.c_char_p
 _lib.dock_version.restype = C.c_int32
 _SIGS = {
-    "dock_create_pocket": [_P, _P, C.c_int32, _P, C.c_int32, _P],
-    "dock_create_pocket_from_receptor": [_P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P],
+    "dock_create_pocket": [_P, _P, C.c_int32, _P, C.c_int32, C.c_int32, _P],
+    "dock_create_pocket_from_receptor": [_P, _P, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, _P],
+    "dock_pocket_layout": [_P, _P],
     "dock_pocket_maps": [_P, _P, _P],
     "dock_destroy_pocket": [_P],
     "dock_create_ligands": [_P, _P, C.c_int32, _P],
@@ -75,6 +77,8 @@ _SIGS = {
     "dock_de_init": [_P, _P, C.c_int32, _P, _P],
     "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
+    "dock_gather_probe": [_P, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
+    "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -142,6 +146,12 @@ class Pocket:
         self.grid = grid
         self.device = device
 
+    @property
+    def layout(self) -> int:
+        out = C.c_int32(0)
+        _check(_lib.dock_pocket_layout(self.handle, C.byref(out)))
+        return out.value
+
     def __del__(self):
         if getattr(self, "handle", None):
             _lib.dock_destroy_pocket(self.handle)
@@ -168,7 +178,7 @@ class Ligands:
             self.handle = None
 
 
-def dock_create_pocket(grid, maps, ff, device: int = 0) -> Pocket:
+def dock_create_pocket(grid, maps, ff, device: int = 0, layout: int = DOCK_LAYOUT_AUTO) -> Pocket:
     """maps: host numpy array or device tensor, float32 [n_types+2, nz, ny, nx]."""
     keep = _Keep()
     F = _ff_struct(ff, keep)
@@ -178,11 +188,11 @@ def dock_create_pocket(grid, maps, ff, device: int = 0) -> Pocket:
         ptr, on_dev = keep.arr(maps, np.float32), 0
     else:
         ptr, on_dev = _dptr(maps, "float32", "maps"), 1
-    _check(_lib.dock_create_pocket(C.byref(G), ptr, on_dev, C.byref(F), device, C.byref(out)))
+    _check(_lib.dock_create_pocket(C.byref(G), ptr, on_dev, C.byref(F), layout, device, C.byref(out)))
     return Pocket(out, grid, device)
 
 
-def dock_create_pocket_from_receptor(grid, ff, receptor, device: int = 0) -> Pocket:
+def dock_create_pocket_from_receptor(grid, ff, receptor, device: int = 0, layout: int = DOCK_LAYOUT_AUTO) -> Pocket:
     keep = _Keep()
     F = _ff_struct(ff, keep)
     G = _grid_struct(grid)
@@ -190,7 +200,8 @@ def dock_create_pocket_from_receptor(grid, ff, receptor, device: int = 0) -> Poc
     n = int(len(receptor.type))
     _check(_lib.dock_create_pocket_from_receptor(C.byref(G), C.byref(F), n, keep.arr(receptor.xyz, np.float32),
                                                  keep.arr(receptor.type, np.int32),
-                                                 keep.arr(receptor.charge, np.float32), device, C.byref(out)))
+                                                 keep.arr(receptor.charge, np.float32), layout, device,
+                                                 C.byref(out)))
     return Pocket(out, grid, device)
 
 
@@ -260,3 +271,17 @@ def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population,
                             _dptr(best_genotypes, "float32", "best_genotypes"),
                             _dptr(best_energies, "float32", "best_energies"), _dptr(target, "float32", "target"),
                             _dptr(gen_reached, "int32", "gen_reached"), _stream(stream)))
+
+
+def dock_gather_probe(pocket: Pocket, box_lo, box_hi, out, per_lane: int, seed: int = 1, stream=None):
+    """Random map lookups alone (roofline probe); out: float32 device tensor, one value per lane."""
+    lo = (C.c_float * 3)(*box_lo)
+    hi = (C.c_float * 3)(*box_hi)
+    _check(_lib.dock_gather_probe(pocket.handle, lo, hi, int(out.numel()), per_lane, seed,
+                                  _dptr(out, "float32", "out"), _stream(stream)))
+
+
+def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):
+    """Pair terms alone on register coordinates (roofline probe)."""
+    _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane, _dptr(out, "float32", "out"),
+                                _stream(stream)))

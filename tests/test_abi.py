@@ -36,7 +36,8 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_abi():
     from paper_2509_12232_amd import dock
     for n in declared_entry_points():
-        if n in ("dock_last_error", "dock_destroy_pocket", "dock_destroy_ligands", "dock_ligand_pair_count"):
+        if n in ("dock_last_error", "dock_destroy_pocket", "dock_destroy_ligands", "dock_ligand_pair_count",
+                 "dock_pocket_layout"):
             continue
         assert hasattr(dock, n), n
 
@@ -46,7 +47,7 @@ def test_host_only_calls():
     assert dock.dock_version() == 1
     lib = dock._lib
     # a null out-pointer is rejected on the host before any device work
-    st = lib.dock_create_pocket(None, None, 0, None, 0, None)
+    st = lib.dock_create_pocket(None, None, 0, None, -1, 0, None)
     assert st == dock.DOCK_E_INVALID
     assert b"null" in lib.dock_last_error()
     assert lib.dock_destroy_pocket(None) == dock.DOCK_OK

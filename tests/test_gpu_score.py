@@ -28,12 +28,15 @@ def _gpu_energies(dk, pocket, ligs, g, pose_ligand=None):
     return e.cpu().numpy()
 
 
-def test_config0_single_ligand_parity(dk, ora):
-    """24-atom, 6-torsion ligand on 40^3 maps: 4133 random poses (64 full tiles + a ragged tail)."""
+@pytest.mark.parametrize("layout", [0, 1, 2])
+def test_config0_single_ligand_parity(dk, ora, layout):
+    """24-atom, 6-torsion ligand on 40^3 maps: 4133 random poses (64 full tiles +
+    a ragged tail), for each device map layout."""
     ff, rec, grid, maps = system(0)
     lig = synth.make_ligand(1, 0, 24, 6, 8)
-    print("case: config0 single ligand, 4133 poses", flush=True)
-    pocket = dk.dock_create_pocket(grid, maps, ff)
+    print("case: config0 single ligand, 4133 poses, layout", layout, flush=True)
+    pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+    assert pocket.layout == layout
     ligs = dk.dock_create_ligands(pocket, [lig])
     lo, hi = synth.pocket_box(grid)
     g = synth.sample_genotypes(11, 4133, 6, 13, lo, hi)

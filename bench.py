@@ -12,6 +12,7 @@ oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -63,6 +64,74 @@ def setup(n_poses: int, seed: int = 1):
                 n_pairs=ligs.pair_count(0))
 
 
+def kernel_source_hash() -> str:
+    """Hash of the scoring kernel's sources; HBM traffic figures recorded under
+    profiles/ are used only while it matches."""
+    h = hashlib.sha256()
+    for f in ("score.hip", "score_pose.h", "dock_internal.h"):
+        with open(os.path.join(ROOT, "paper_2509_12232_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(n_poses: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (scaled by the copy-kernel calibration), or None if the kernel has
+    changed since it was taken or the workload differs."""
+    path = os.path.join(ROOT, "profiles", "score_kernel_config1_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_hash") != kernel_source_hash() or int(kv.get("poses", "0")) != n_poses:
+        return None
+    return float(kv["traffic_bytes"])
+
+
+def probes(S, kernel_ms: float, n_poses: int):
+    """Measured ceilings at the same spatial distribution: map lookups alone
+    (gather probe: random rigid placements of the ligand's atoms with
+    translations in the pocket box) and pair terms alone (pair probe)."""
+    import torch
+    dk = S["dk"]
+    lig = S["lig"]
+    blo, bhi = synth.pocket_box(S["grid"])
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    lanes, per = 1 << 21, 128
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    g_ms = timeit(lambda: dk.dock_gather_probe(S["pocket"], S["ligs"], 0, blo, bhi, out, per))
+    probe_lps = lanes * per / (g_ms * 1e-3)
+    lanes, per = 1 << 20, 1024
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    p_ms = timeit(lambda: dk.dock_pair_probe(S["pocket"], out, per))
+    probe_pps = lanes * per / (p_ms * 1e-3)
+    kernel_lps = lig.n_atoms * n_poses / (kernel_ms * 1e-3)
+    kernel_pps = S["n_pairs"] * n_poses / (kernel_ms * 1e-3)
+    return {
+        "gather": {"unit": "lookups/s", "kernel": round(kernel_lps, -6), "probe": round(probe_lps, -6),
+                   "frac": round(kernel_lps / probe_lps, 4),
+                   "probe_kind": "rigid random placements of the ligand's atoms, translations in the pocket box"},
+        "pairs": {"unit": "pair terms/s", "kernel": round(kernel_pps, -6), "probe": round(probe_pps, -6),
+                  "frac": round(kernel_pps / probe_pps, 4)},
+    }
+
+
 def cpu_baseline(S, target_seconds: float, max_poses: int):
     """The FP64 oracle on the host cores, on a prefix of the same genotypes."""
     import oracle
@@ -92,6 +161,9 @@ def main():
     ap.add_argument("--poses", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3 counter runs: one 1 GiB device copy (calibration of the "
+                         "FETCH_SIZE/WRITE_SIZE counters) and two scoring steps, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the workload shards by pose range "
@@ -106,6 +178,17 @@ def main():
 
     def step():
         dk.dock_score_poses(S["pocket"], S["ligs"], S["gt"], S["e"])
+
+    if args.profile:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        step()
+        step()
+        torch.cuda.synchronize()
+        log("profile run: 1 GiB copy, 2 scoring steps")
+        return
 
     for _ in range(args.warmup):
         step()
@@ -131,11 +214,13 @@ def main():
     gather_gbs = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     flops_per_launch = FLOPS_PER_PAIR * S["n_pairs"] * n
     tflops = flops_per_launch / (kernel_ms * 1e-3) / 1e12
+    traffic = recorded_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gather_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4),
+                "frac": round(gather_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
                 "alu": {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}}
+                        "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},
+                "measured": probes(S, kernel_ms, n)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -147,7 +232,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(S, args.cpu_seconds, 400_000)
+        out["cpu_baseline"] = cpu_baseline(S, args.cpu_seconds, n)
     print(json.dumps(out), flush=True)
 
 

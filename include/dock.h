@@ -216,15 +216,18 @@ dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, con
 /* ---- Roofline probes: measurement aids, not steps of the docking path. ---- */
 
 /* Map lookups alone, as the inter-energy loop of Algorithm 2 performs them: each
- * of n_lanes lanes interpolates per_lane atoms placed uniformly at random in the
- * box [box_lo, box_hi] (host float[3] each), with random types and charges,
- * through the pocket's device layout and the scoring kernel's gather code, and
- * writes the sum of its values to out[lane] (device float[n_lanes]).  Timing it
- * gives the measured rate of random lookups at this map footprint.  Errors:
- * DOCK_E_INVALID (null pointers, empty box, n_lanes outside 1..2^31, per_lane
- * not a positive multiple of 4), DOCK_E_DEVICE. */
-dock_status dock_gather_probe(const dock_pocket *pocket, const float box_lo[3], const float box_hi[3],
-                              int64_t n_lanes, int32_t per_lane, uint64_t seed, float *out, void *stream);
+ * of n_lanes lanes interpolates per_lane atoms of ligand lig, each a random atom
+ * of its reference conformation placed rigidly with a random orientation and a
+ * translation uniform in [box_lo, box_hi] (host float[3] each), through the
+ * pocket's device layout and the scoring kernel's gather code, and writes the
+ * sum of its values to out[lane] (device float[n_lanes]).  Timing it gives the
+ * measured rate of random lookups for that workload's spatial distribution.
+ * Errors: DOCK_E_INVALID (null pointers, handles of different devices, lig out
+ * of range, empty box, n_lanes outside 1..2^31, per_lane not a positive
+ * multiple of 4), DOCK_E_DEVICE. */
+dock_status dock_gather_probe(const dock_pocket *pocket, const dock_ligands *ligs, int32_t lig,
+                              const float box_lo[3], const float box_hi[3], int64_t n_lanes, int32_t per_lane,
+                              uint64_t seed, float *out, void *stream);
 
 /* Intra-energy pair terms alone (Algorithm 2's pair loop body) on register
  * coordinates: n_lanes lanes evaluate per_lane 12-6 pair terms each with the

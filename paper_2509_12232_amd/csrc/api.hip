@@ -11,6 +11,7 @@
 
 #include "dock.h"
 #include "dock_internal.h"
+#include "probe.h"
 
 using namespace dock;
 
@@ -714,10 +715,13 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
 }
 
 // ------------------------------------------------------------------------------ probes
-extern "C" dock_status dock_gather_probe(const dock_pocket *p, const float box_lo[3], const float box_hi[3],
-                                         int64_t n_lanes, int32_t per_lane, uint64_t seed, float *out,
-                                         void *stream) {
-  if (!p || !box_lo || !box_hi || !out) return set_err(DOCK_E_INVALID, "null argument");
+extern "C" dock_status dock_gather_probe(const dock_pocket *p, const dock_ligands *L, int32_t lig,
+                                         const float box_lo[3], const float box_hi[3], int64_t n_lanes,
+                                         int32_t per_lane, uint64_t seed, float *out, void *stream) {
+  dock_status st = check_pair(p, L);
+  if (st) return st;
+  if (!box_lo || !box_hi || !out) return set_err(DOCK_E_INVALID, "null argument");
+  if (lig < 0 || lig >= L->n_ligs) return set_err(DOCK_E_INVALID, "ligand index out of range");
   if (n_lanes < 1 || n_lanes > ((int64_t)1 << 31) || per_lane < 4 || per_lane % 4)
     return set_err(DOCK_E_INVALID, "n_lanes in 1..2^31, per_lane a positive multiple of 4");
   ProbeBox box{};
@@ -728,8 +732,8 @@ extern "C" dock_status dock_gather_probe(const dock_pocket *p, const float box_l
   }
   DeviceScope ds(p->device);
   HIP_TRY(ds.err, "hipSetDevice");
-  HIP_TRY(launch_gather_probe(p->geom, p->view(), p->layout, box, n_lanes, per_lane, (uint32_t)seed, out,
-                              (hipStream_t)stream),
+  HIP_TRY(launch_gather_probe(p->geom, p->view(), p->layout, L->view(), lig, box, n_lanes, per_lane,
+                              (uint32_t)seed, out, (hipStream_t)stream),
           "gather probe launch");
   return DOCK_OK;
 }

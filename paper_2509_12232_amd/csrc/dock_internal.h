@@ -145,15 +145,3 @@ hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, v
 
 }  // namespace dock
 
-namespace dock {
-
-// Box for the gather probe's positions.
-struct ProbeBox {
-  float lo[3], ext[3];
-};
-
-hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const ProbeBox &box,
-                               int64_t n_lanes, int32_t per_lane, uint32_t seed, float *out, hipStream_t s);
-hipError_t launch_pair_probe(const FFConst &F, int64_t n_lanes, int32_t per_lane, float *out, hipStream_t s);
-
-}  // namespace dock

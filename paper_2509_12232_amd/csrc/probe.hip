@@ -1,14 +1,17 @@
 // probe.hip -- roofline probes for the scoring kernel's two halves.
 //
 // gather_probe: the inter-energy lookups alone (Algorithm 2's map lookups):
-// each lane interpolates atoms at positions drawn uniformly in a box, with
-// uniform types and charges, through the same layout and gather code as the
-// scoring kernel, at full occupancy and with no other work.  Its rate is the
-// measured ceiling for random map lookups at this map footprint.
+// each lane interpolates atoms of one ligand placed rigidly at random (a
+// translation uniform in a box, a random orientation, a random atom of the
+// ligand's reference conformation), through the same layout and gather code
+// as the scoring kernel, at full occupancy and with no other work.  Its rate
+// is the measured ceiling for the lookups of that workload's spatial
+// distribution (torsional flexibility aside).
 //
 // pair_probe: the intra-energy pair term alone on register-resident
 // coordinates, at full occupancy: the measured VALU ceiling for pair terms.
 #include "dock_internal.h"
+#include "probe.h"
 #include "score_pose.h"
 
 namespace dock {
@@ -27,10 +30,14 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __device__ __forceinline__ float unit01(uint32_t h) { return (float)(h >> 8) * (1.0f / 16777216.0f); }
 
 template <int LAYOUT>
-__global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M, ProbeBox box, int per_lane,
-                                                            uint32_t seed, int64_t n_lanes, float *out) {
+__global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M, LigandsDev L, int lig, ProbeBox box,
+                                                            int per_lane, uint32_t seed, int64_t n_lanes,
+                                                            float *out) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if ((int64_t)t >= n_lanes) return;
+  const LigHeader H = L.hdr[lig];
+  const float4 *__restrict__ atoms = L.atoms + H.atom_off;
+  const int32_t *__restrict__ types = L.atom_type + H.atom_off;
   float acc = 0.f;
   constexpr int U = 4;  // lookups in flight per lane
   for (int m = 0; m < per_lane; m += U) {
@@ -38,12 +45,20 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t h = mix32(seed ^ mix32(t * 0x9E3779B9u + (uint32_t)(m + u)));
-      const float px = box.lo[0] + box.ext[0] * unit01(mix32(h + 1));
-      const float py = box.lo[1] + box.ext[1] * unit01(mix32(h + 2));
-      const float pz = box.lo[2] + box.ext[2] * unit01(mix32(h + 3));
-      const int type = (int)(h % (uint32_t)G.n_types);
-      const float q = unit01(h) - 0.5f;
-      c[u] = gather_corners<LAYOUT>(G, M, type, q, px, py, pz);
+      const float tx = box.lo[0] + box.ext[0] * unit01(mix32(h + 1));
+      const float ty = box.lo[1] + box.ext[1] * unit01(mix32(h + 2));
+      const float tz = box.lo[2] + box.ext[2] * unit01(mix32(h + 3));
+      // orientation: normalised point of the cube [-1,1]^4 (isotropic enough for a footprint)
+      float qw = 2.f * unit01(mix32(h + 4)) - 1.f, qx = 2.f * unit01(mix32(h + 5)) - 1.f;
+      float qy = 2.f * unit01(mix32(h + 6)) - 1.f, qz = 2.f * unit01(mix32(h + 7)) - 1.f;
+      const float r = __builtin_amdgcn_rsqf(fmaxf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))), 1e-12f));
+      qw *= r; qx *= r; qy *= r; qz *= r;
+      const int i = (int)(h % (uint32_t)H.n_atoms);
+      const float4 a = atoms[i];
+      const float px = fmaf(1.f - 2.f * (qy * qy + qz * qz), a.x, fmaf(2.f * (qx * qy - qw * qz), a.y, fmaf(2.f * (qx * qz + qw * qy), a.z, tx)));
+      const float py = fmaf(2.f * (qx * qy + qw * qz), a.x, fmaf(1.f - 2.f * (qx * qx + qz * qz), a.y, fmaf(2.f * (qy * qz - qw * qx), a.z, ty)));
+      const float pz = fmaf(2.f * (qx * qz - qw * qy), a.x, fmaf(2.f * (qy * qz + qw * qx), a.y, fmaf(1.f - 2.f * (qx * qx + qy * qy), a.z, tz)));
+      c[u] = gather_corners<LAYOUT>(G, M, types[i], a.w, px, py, pz);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc += interpolate_corners<LAYOUT>(c[u]);
@@ -51,18 +66,22 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
   out[t] = acc;
 }
 
-hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const ProbeBox &box,
-                               int64_t n_lanes, int32_t per_lane, uint32_t seed, float *out, hipStream_t s) {
+hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const LigandsDev &L,
+                               int32_t lig, const ProbeBox &box, int64_t n_lanes, int32_t per_lane,
+                               uint32_t seed, float *out, hipStream_t s) {
   const unsigned blocks = (unsigned)((n_lanes + 255) / 256);
   switch (layout) {
     case kLinear:
-      hipLaunchKernelGGL(gather_probe_kernel<kLinear>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      hipLaunchKernelGGL(gather_probe_kernel<kLinear>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
+                         seed, n_lanes, out);
       break;
     case kZPair:
-      hipLaunchKernelGGL(gather_probe_kernel<kZPair>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      hipLaunchKernelGGL(gather_probe_kernel<kZPair>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
+                         seed, n_lanes, out);
       break;
     case kYZQuad:
-      hipLaunchKernelGGL(gather_probe_kernel<kYZQuad>, dim3(blocks), dim3(256), 0, s, G, M, box, per_lane, seed, n_lanes, out);
+      hipLaunchKernelGGL(gather_probe_kernel<kYZQuad>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
+                         seed, n_lanes, out);
       break;
     default:
       return hipErrorInvalidValue;

@@ -77,7 +77,7 @@ _SIGS = {
     "dock_de_init": [_P, _P, C.c_int32, _P, _P],
     "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
-    "dock_gather_probe": [_P, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
+    "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
 }
 for _name, _args in _SIGS.items():
@@ -273,11 +273,12 @@ def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population,
                             _dptr(gen_reached, "int32", "gen_reached"), _stream(stream)))
 
 
-def dock_gather_probe(pocket: Pocket, box_lo, box_hi, out, per_lane: int, seed: int = 1, stream=None):
+def dock_gather_probe(pocket: Pocket, ligs: Ligands, lig: int, box_lo, box_hi, out, per_lane: int, seed: int = 1,
+                      stream=None):
     """Random map lookups alone (roofline probe); out: float32 device tensor, one value per lane."""
     lo = (C.c_float * 3)(*box_lo)
     hi = (C.c_float * 3)(*box_hi)
-    _check(_lib.dock_gather_probe(pocket.handle, lo, hi, int(out.numel()), per_lane, seed,
+    _check(_lib.dock_gather_probe(pocket.handle, ligs.handle, lig, lo, hi, int(out.numel()), per_lane, seed,
                                   _dptr(out, "float32", "out"), _stream(stream)))
 
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -79,6 +80,7 @@ struct dock_pocket {
   float *maps = nullptr;      // ABI layout
   int64_t plane = 0;
   int32_t layout = kLinear;    // layout the scoring kernel reads
+  int32_t n_cu = 1;            // compute units of the device (persistent launch size)
   void *tpack = nullptr;       // packed type maps
   float4 *edpack = nullptr;    // packed electrostatic/desolvation records
   int64_t t_stride = 0;
@@ -133,6 +135,13 @@ static void free_pocket(dock_pocket *p) {
   delete p;
 }
 
+// Ligands with (previous bucket's upper, upper] atoms: order[offset .. offset + count).
+struct LigandBucket {
+  int32_t upper;      // atom-count bound of the bucket
+  int32_t lds_atoms;  // largest ligand actually in it (sizes the LDS of its launch)
+  int32_t offset, count;
+};
+
 struct dock_ligands {
   int device = 0;
   int n_ligs = 0;
@@ -144,6 +153,21 @@ struct dock_ligands {
   int32_t *atom_type = nullptr;
   TorRec *tors = nullptr;
   PairRec *pairs = nullptr;
+  // ligands grouped by atom count; within a group, costliest first
+  std::vector<LigandBucket> buckets;
+  int32_t *order = nullptr;
+  // side streams for concurrent bucket launches (created on first use)
+  mutable std::mutex side_mu;
+  mutable std::vector<hipStream_t> side;
+  hipError_t ensure_side_streams() const {
+    while (side.size() < 4) {
+      hipStream_t st = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+      side.push_back(st);
+    }
+    return hipSuccess;
+  }
   LigandsDev view() const { return LigandsDev{hdr, atoms, atom_type, tors, pairs, n_ligs}; }
 };
 
@@ -205,6 +229,13 @@ static void fill_pocket_ff(dock_pocket *p, const dock_forcefield *ff) {
   c.pad = 0;
 }
 
+static hipError_t fill_device_info(dock_pocket *p) {
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, p->device);
+  if (e == hipSuccess) p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  return e;
+}
+
 static void fill_geom(dock_pocket *p, const dock_grid *g) {
   p->geom = MapGeom{g->dims[0], g->dims[1], g->dims[2], g->n_types, g->origin[0], g->origin[1], g->origin[2],
                     (float)(1.0 / (double)g->spacing)};
@@ -228,7 +259,8 @@ extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *ma
   fill_pocket_ff(p, ff);
   fill_geom(p, grid);
   const size_t bytes = sizeof(float) * p->plane * (ff->n_types + 2);
-  hipError_t e = hipMalloc((void **)&p->maps, bytes);
+  hipError_t e = fill_device_info(p);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->maps, bytes);
   if (e == hipSuccess)
     e = hipMemcpy(p->maps, maps, bytes, maps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
   if (e == hipSuccess) e = pack_maps(p, layout);
@@ -279,7 +311,8 @@ extern "C" dock_status dock_create_pocket_from_receptor(const dock_grid *grid, c
   float4 *d_rec = nullptr;
   int32_t *d_rt = nullptr, *d_hb = nullptr;
   float *d_A = nullptr, *d_B = nullptr, *d_sol = nullptr, *d_vol = nullptr;
-  hipError_t e = upload(&d_rec, rec);
+  hipError_t e = fill_device_info(p);
+  if (e == hipSuccess) e = upload(&d_rec, rec);
   if (e == hipSuccess) e = upload(&d_rt, rt);
   if (e == hipSuccess) e = upload(&d_A, A);
   if (e == hipSuccess) e = upload(&d_B, B);
@@ -494,7 +527,9 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
 }  // namespace
 
 static void free_ligands(dock_ligands *L) {
-  for (void *q : {(void *)L->hdr, (void *)L->atoms, (void *)L->atom_type, (void *)L->tors, (void *)L->pairs})
+  for (hipStream_t st : L->side) (void)hipStreamDestroy(st);
+  for (void *q : {(void *)L->hdr, (void *)L->atoms, (void *)L->atom_type, (void *)L->tors, (void *)L->pairs,
+                  (void *)L->order})
     if (q) (void)hipFree(q);
   delete L;
 }
@@ -543,11 +578,29 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   L->max_tors = max_tors;
   L->hdr_host = hdr;
   L->pair_count = pair_count;
+  // size buckets for the search launches (LDS is sized per bucket); the work of a
+  // ligand's search grows with atoms + pairs, and the costliest go first
+  std::vector<int32_t> order;
+  int lo = 0;
+  for (int ub : {16, 32, 48, 64, kMaxAtoms}) {
+    std::vector<int32_t> ids;
+    for (int l = 0; l < n_ligands; ++l)
+      if (hdr[l].n_atoms > lo && hdr[l].n_atoms <= ub) ids.push_back(l);
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+      return hdr[x].n_atoms + pair_count[x] > hdr[y].n_atoms + pair_count[y];
+    });
+    int mx = 1;
+    for (int32_t l : ids) mx = std::max(mx, hdr[l].n_atoms);
+    L->buckets.push_back(LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size()});
+    order.insert(order.end(), ids.begin(), ids.end());
+    lo = ub;
+  }
   hipError_t e = upload(&L->hdr, hdr);
   if (e == hipSuccess) e = upload(&L->atoms, atoms);
   if (e == hipSuccess) e = upload(&L->atom_type, types);
   if (e == hipSuccess) e = upload(&L->tors, tors);
   if (e == hipSuccess) e = upload(&L->pairs, pairs);
+  if (e == hipSuccess) e = upload(&L->order, order);
   if (e != hipSuccess) {
     free_ligands(L);
     return hip_err(e, "ligand upload");
@@ -676,41 +729,64 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   DeviceScope ds(p->device);
   HIP_TRY(ds.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  const DEParams dp = de_params(q);
   const int nl = L->n_ligs, P = q->pop_size;
   const int64_t n = (int64_t)nl * P;
-  ScoreLaunch a = make_score(p, L);
-  a.pose_ligand = nullptr;
-  a.poses_per_ligand = P;
-  a.g_stride = g_stride;
-  a.n_poses = n;
-  const bool track = target && gen_reached;
-  if (q->init) {
-    HIP_TRY(launch_de_init(L->view(), dp, g_stride, population, s), "de_init launch");
-    a.genotypes = population;
-    a.energies = pop_energy;
-    HIP_TRY(launch_score(a, s), "score launch");
-  }
-  if (track) HIP_TRY(launch_de_check(nl, P, pop_energy, target, gen_reached, q->first_generation, q->init, s), "check");
-  if (q->n_generations > 0) {
-    float *trials = nullptr, *trial_e = nullptr;
-    HIP_TRY(hipMallocAsync((void **)&trials, sizeof(float) * n * g_stride, s), "trial buffer");
-    hipError_t e = hipMallocAsync((void **)&trial_e, sizeof(float) * n, s);
-    for (int g = q->first_generation; e == hipSuccess && g < q->first_generation + q->n_generations; ++g) {
-      e = launch_de_trials(L->view(), dp, g, g_stride, population, trials, s);
-      if (e != hipSuccess) break;
-      a.genotypes = trials;
-      a.energies = trial_e;
-      e = launch_score(a, s);
-      if (e != hipSuccess) break;
-      e = launch_de_select(nl, P, g_stride, population, pop_energy, trials, trial_e, track ? target : nullptr,
-                           track ? gen_reached : nullptr, g + 1, s);
+  SearchLaunch S{};
+  S.L = L->view();
+  S.geom = p->geom;
+  S.ff = p->ffc;
+  S.maps = p->view();
+  S.p = de_params(q);
+  S.g_stride = g_stride;
+  S.init = q->init ? 1 : 0;
+  S.population = population;
+  S.pop_energy = pop_energy;
+  S.best_g = best_genotypes;
+  S.best_e = best_energies;
+  S.target = (target && gen_reached) ? target : nullptr;
+  S.gen_reached = (target && gen_reached) ? gen_reached : nullptr;
+  const int nb = (int)L->buckets.size();
+  int32_t *queues = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s), "trial buffer");
+  hipError_t e = hipMallocAsync((void **)&queues, sizeof(int32_t) * nb, s);
+  if (e == hipSuccess) e = launch_fill_i32(queues, nb, 0, s);
+  // The size buckets run concurrently on the handle's side streams (forked from
+  // and joined back to the caller's stream), so that small buckets do not leave
+  // the GPU idle while the last ligands of another bucket finish.
+  std::lock_guard<std::mutex> guard(L->side_mu);
+  if (e == hipSuccess) e = L->ensure_side_streams();
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  const char *step = "side streams";
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, s);
+  int k = 0;
+  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+    const LigandBucket &B = L->buckets[b];
+    if (B.count == 0) continue;
+    hipStream_t side = L->side[k++ % L->side.size()];
+    e = hipStreamWaitEvent(side, fork, 0);
+    S.order = L->order + B.offset;
+    S.n_order = B.count;
+    S.queue = queues + b;
+    S.lds_atoms = B.lds_atoms;
+    if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, side, &step);
+    hipEvent_t done = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e == hipSuccess) {
+      joins.push_back(done);
+      e = hipEventRecord(done, side);
     }
-    if (trial_e) (void)hipFreeAsync(trial_e, s);
-    (void)hipFreeAsync(trials, s);
-    if (e != hipSuccess) return hip_err(e, "search loop");
   }
-  HIP_TRY(launch_de_best(nl, P, g_stride, population, pop_energy, best_genotypes, best_energies, s), "best");
+  for (hipEvent_t ev : joins) {
+    hipError_t w = hipStreamWaitEvent(s, ev, 0);
+    if (e == hipSuccess) e = w;
+    (void)hipEventDestroy(ev);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (queues) (void)hipFreeAsync(queues, s);
+  (void)hipFreeAsync(S.trials, s);
+  if (e != hipSuccess) return hip_err(e, step);
   return DOCK_OK;
 }
 

@@ -34,7 +34,7 @@ struct DrawStream {
   uint64_t seed, c0, c1, c2, purpose;
   uint64_t n;
   uint64_t blk;            // index of the cached block (~0 = none)
-  uint64_t w[4];
+  uint64_t w0, w1, w2, w3;  // the cached block (named, so it stays in registers)
 
   __device__ DrawStream(uint64_t seed_, uint64_t indiv, uint64_t gen, uint64_t lig, uint64_t purpose_)
       : seed(seed_), c0(indiv), c1(gen), c2(lig), purpose(purpose_), n(0), blk(~0ull) {}
@@ -42,11 +42,12 @@ struct DrawStream {
   __device__ __forceinline__ uint32_t u32() {
     const uint64_t b = n >> 3;
     if (b != blk) {
-      w[0] = c0; w[1] = c1; w[2] = c2; w[3] = (purpose << 32) | b;
-      philox4x64_10(w[0], w[1], w[2], w[3], seed, 0);
+      w0 = c0; w1 = c1; w2 = c2; w3 = (purpose << 32) | b;
+      philox4x64_10(w0, w1, w2, w3, seed, 0);
       blk = b;
     }
-    const uint64_t word = w[(n >> 1) & 3];
+    const uint32_t k = (uint32_t)(n >> 1) & 3u;
+    const uint64_t word = k == 0 ? w0 : k == 1 ? w1 : k == 2 ? w2 : w3;
     const uint32_t v = (n & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
     ++n;
     return v;

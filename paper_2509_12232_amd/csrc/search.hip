@@ -4,8 +4,17 @@
 // The floating-point steps that decide a genotype are done in binary64 with
 // contraction switched off, so that every trial genotype is a reproducible
 // function of (seed, population, generation, ligand, individual).
+//
+// dock_search runs one persistent kernel per ligand-size bucket: each workgroup
+// (up to four wavefronts) takes the next ligand from a work queue (largest
+// first) and runs its whole search -- initial population, then per generation
+// all trials, their scores and the greedy selection -- with one lane per
+// individual, and no other launch or host round trip.
+#include <algorithm>
+
 #include "dock_internal.h"
 #include "philox.h"
+#include "score_pose.h"
 
 namespace dock {
 
@@ -92,6 +101,7 @@ __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen,
   }
 }
 
+
 __global__ void de_init_kernel(LigandsDev L, DEParams p, int g_stride, float *pop) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)L.n_ligs * p.pop) return;
@@ -107,63 +117,108 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
   trial_individual(p, L.hdr[lig].n_tors, lig, gen, i, g_stride, base, trials + t * g_stride);
 }
 
-// One block per ligand: greedy replacement, then the target check.
-__global__ void de_select_kernel(int pop, int g_stride, float *population, float *pop_energy,
-                                 const float *trials, const float *trial_energy, const float *target,
-                                 int32_t *gen_reached, int gen_done) {
-  const int lig = blockIdx.x;
-  float *P = population + (int64_t)lig * pop * g_stride;
-  float *E = pop_energy + (int64_t)lig * pop;
-  const float *T = trials + (int64_t)lig * pop * g_stride;
-  const float *ET = trial_energy + (int64_t)lig * pop;
-  int hit = 0;
-  const float tg = (target && gen_reached) ? target[lig] : 0.f;
-  for (int i = threadIdx.x; i < pop; i += blockDim.x) {
-    const float et = ET[i];
-    float e = E[i];
-    if (et <= e) {
-      for (int j = 0; j < g_stride; ++j) P[(int64_t)i * g_stride + j] = T[(int64_t)i * g_stride + j];
-      E[i] = et;
-      e = et;
+// The whole search of one ligand, run by one workgroup (lane t handles
+// individuals t, t + blockDim.x, ...).
+template <int LAYOUT>
+__device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
+  const int t = threadIdx.x, NT = blockDim.x;
+  const LigHeader H = S.L.hdr[lig];
+  const int P = S.p.pop, G = S.g_stride;
+  float *pop = S.population + (int64_t)lig * P * G;
+  float *E = S.pop_energy + (int64_t)lig * P;
+  float *T = S.trials + (int64_t)lig * P * G;
+  const bool track = S.target != nullptr && S.gen_reached != nullptr;
+  const float tgt = track ? S.target[lig] : 0.f;
+  if (S.init) {
+    for (int c = 0; c < P; c += NT) {
+      const int i = c + t;
+      if (i < P) {
+        float *row = pop + (int64_t)i * G;
+        init_individual(S.p, H.n_tors, lig, i, G, row);
+        E[i] = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, row, my);
+      }
     }
-    if (target && gen_reached) hit |= (e <= tg);
   }
-  if (target && gen_reached) {
+  int reached = -1;
+  if (track) {
+    int hit = 0;
+    for (int c = 0; c < P; c += NT) {
+      const int i = c + t;
+      if (i < P) hit |= E[i] <= tgt;
+    }
     hit = __syncthreads_or(hit);
-    if (threadIdx.x == 0 && hit && gen_reached[lig] < 0) gen_reached[lig] = gen_done;
-  }
-}
-
-__global__ void de_check_kernel(int pop, const float *pop_energy, const float *target, int32_t *gen_reached,
-                                int gen_done, int reset) {
-  const int lig = blockIdx.x;
-  const float *E = pop_energy + (int64_t)lig * pop;
-  int hit = 0;
-  for (int i = threadIdx.x; i < pop; i += blockDim.x) hit |= (E[i] <= target[lig]);
-  hit = __syncthreads_or(hit);
-  if (threadIdx.x == 0) {
-    int32_t r = reset ? -1 : gen_reached[lig];
-    if (r < 0 && hit) r = gen_done;
-    gen_reached[lig] = r;
-  }
-}
-
-// Best member of the final population: first index of the smallest energy.
-__global__ void de_best_kernel(int pop, int g_stride, const float *population, const float *pop_energy,
-                               float *best_g, float *best_e) {
-  const int lig = blockIdx.x;
-  const float *E = pop_energy + (int64_t)lig * pop;
-  __shared__ int s_bi;
-  if (threadIdx.x == 0) {
-    int bi = 0;
-    for (int i = 1; i < pop; ++i)
-      if (E[i] < E[bi]) bi = i;
-    s_bi = bi;
-    best_e[lig] = E[bi];
+    reached = S.init ? -1 : S.gen_reached[lig];
+    if (reached < 0 && hit) reached = S.p.first_gen;
   }
   __syncthreads();
-  const float *row = population + ((int64_t)lig * pop + s_bi) * g_stride;
-  for (int j = threadIdx.x; j < g_stride; j += blockDim.x) best_g[(int64_t)lig * g_stride + j] = row[j];
+  for (int g = S.p.first_gen; g < S.p.first_gen + S.p.n_gen; ++g) {
+    // every trial of the generation is drawn from the population as it stood
+    for (int c = 0; c < P; c += NT) {
+      const int i = c + t;
+      if (i < P) trial_individual(S.p, H.n_tors, lig, g, i, G, pop, T + (int64_t)i * G);
+    }
+    __syncthreads();
+    int hit = 0;
+    for (int c = 0; c < P; c += NT) {
+      const int i = c + t;
+      if (i < P) {
+        const float *tr = T + (int64_t)i * G;
+        const float e = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, tr, my);
+        float ei = E[i];
+        if (e <= ei) {
+          float *row = pop + (int64_t)i * G;
+          for (int j = 0; j < G; ++j) row[j] = tr[j];
+          E[i] = e;
+          ei = e;
+        }
+        hit |= ei <= tgt;
+      }
+    }
+    if (track) {
+      hit = __syncthreads_or(hit);
+      if (reached < 0 && hit) reached = g + 1;
+    } else {
+      __syncthreads();
+    }
+  }
+  if (track && t == 0) S.gen_reached[lig] = reached;
+  // best member: first index of the smallest energy
+  __shared__ int s_best;
+  if (t == 0) {
+    int bi = 0;
+    for (int i = 1; i < P; ++i)
+      if (E[i] < E[bi]) bi = i;
+    s_best = bi;
+    S.best_e[lig] = E[bi];
+  }
+  __syncthreads();
+  const int bi = s_best;
+  for (int j = t; j < G; j += NT) S.best_g[(int64_t)lig * G + j] = pop[(int64_t)bi * G + j];
+  __syncthreads();
+}
+
+// Persistent: each workgroup keeps taking ligands from the queue until none is
+// left.  Wavefront w of the group keeps its lanes' coordinates in its own LDS
+// region of lds_atoms * 3 rows of 64 dwords.
+template <int LAYOUT>
+__global__ __launch_bounds__(kSearchMaxThreads, 2) void search_kernel(SearchLaunch S) {
+  extern __shared__ float lds[];
+  __shared__ int s_q;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  float *my = lds + (size_t)wave * 3 * S.lds_atoms * kWave + lane;
+  for (;;) {
+    if (threadIdx.x == 0) s_q = atomicAdd(S.queue, 1);
+    __syncthreads();
+    const int q = s_q;
+    __syncthreads();
+    if (q >= S.n_order) break;
+    search_ligand<LAYOUT>(S, S.order[q], my);
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -181,26 +236,63 @@ hipError_t launch_de_trials(const LigandsDev &L, const DEParams &p, int32_t gen,
   return hipGetLastError();
 }
 
-hipError_t launch_de_select(int32_t n_ligs, int32_t pop, int32_t g_stride, float *population, float *pop_energy,
-                            const float *trials, const float *trial_energy, const float *target,
-                            int32_t *gen_reached, int32_t gen_done, hipStream_t s) {
-  hipLaunchKernelGGL(de_select_kernel, dim3(n_ligs), dim3(256), 0, s, pop, g_stride, population, pop_energy,
-                     trials, trial_energy, target, gen_reached, gen_done);
+hipError_t launch_fill_i32(int32_t *p, int32_t n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 
-hipError_t launch_de_check(int32_t n_ligs, int32_t pop, const float *pop_energy, const float *target,
-                           int32_t *gen_reached, int32_t gen_done, int32_t reset, hipStream_t s) {
-  hipLaunchKernelGGL(de_check_kernel, dim3(n_ligs), dim3(256), 0, s, pop, pop_energy, target, gen_reached,
-                     gen_done, reset);
+template <int LAYOUT>
+static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, hipStream_t s, const char **step) {
+  // Wavefronts per workgroup, w: up to one per 64 individuals.  Each wavefront's
+  // LDS region is sized for the bucket's largest ligand, so a larger w can leave
+  // fewer wavefronts resident per CU.  Pick the w that minimises (rounds of
+  // resident ligands) x (64-individual chunks per ligand per generation).
+  const size_t per_wave = (size_t)S.lds_atoms * 3 * kWave * sizeof(float);
+  const int want = std::min((S.p.pop + kWave - 1) / kWave, kSearchMaxThreads / kWave);
+  // The dynamic LDS allowance is what the CU holds less the kernel's static LDS
+  // (its __shared__ variables plus what the compiler adds for block reductions).
+  hipFuncAttributes fa;
+  *step = "hipFuncGetAttributes";
+  if (hipError_t e = hipFuncGetAttributes(&fa, (const void *)search_kernel<LAYOUT>); e != hipSuccess) return e;
+  if (fa.sharedSizeBytes >= kLdsPerCU) return hipErrorInvalidConfiguration;
+  const size_t max_dyn = kLdsPerCU - fa.sharedSizeBytes;
+  *step = "hipFuncSetAttribute (largest size)";
+  if (per_wave > 65536 || per_wave * want > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)search_kernel<LAYOUT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)std::min<size_t>(max_dyn, per_wave * want));
+    if (e != hipSuccess) return e;
+  }
+  int best_w = 1, best_blocks = 0;
+  int64_t best_cost = -1;
+  for (int w = 1; w <= want; ++w) {
+    if (per_wave * w > max_dyn) break;
+    int blocks = 0;
+    *step = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)search_kernel<LAYOUT>,
+                                                                w * kWave, per_wave * w);
+    if (e != hipSuccess) return e;
+    if (blocks < 1) continue;
+    const int64_t slots = (int64_t)n_cu * blocks;
+    const int64_t rounds = (S.n_order + slots - 1) / slots;
+    const int64_t chunks = (S.p.pop + w * kWave - 1) / (w * kWave);
+    if (best_cost < 0 || rounds * chunks < best_cost) best_cost = rounds * chunks, best_w = w, best_blocks = blocks;
+  }
+  const size_t lds = per_wave * best_w;
+  const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * std::max(best_blocks, 1));
+  *step = "search kernel launch";
+  hipLaunchKernelGGL(search_kernel<LAYOUT>, dim3((unsigned)grid), dim3(best_w * kWave), lds, s, S);
   return hipGetLastError();
 }
 
-hipError_t launch_de_best(int32_t n_ligs, int32_t pop, int32_t g_stride, const float *population,
-                          const float *pop_energy, float *best_g, float *best_e, hipStream_t s) {
-  hipLaunchKernelGGL(de_best_kernel, dim3(n_ligs), dim3(64), 0, s, pop, g_stride, population, pop_energy, best_g,
-                     best_e);
-  return hipGetLastError();
+hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, hipStream_t s, const char **step) {
+  if (S.n_order <= 0) return hipSuccess;
+  switch (layout) {
+    case kLinear: return launch_search_t<kLinear>(S, n_cu, s, step);
+    case kZPair: return launch_search_t<kZPair>(S, n_cu, s, step);
+    case kYZQuad: return launch_search_t<kYZQuad>(S, n_cu, s, step);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dock

@@ -145,6 +145,8 @@ class Pocket:
         self.handle = handle
         self.grid = grid
         self.device = device
+        # held here: module globals may already be gone when __del__ runs at exit
+        self._destroy = _lib.dock_destroy_pocket
 
     @property
     def layout(self) -> int:
@@ -153,8 +155,8 @@ class Pocket:
         return out.value
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.dock_destroy_pocket(self.handle)
+        if getattr(self, "handle", None) and getattr(self, "_destroy", None):
+            self._destroy(self.handle)
             self.handle = None
 
 
@@ -166,6 +168,7 @@ class Ligands:
         self.n = n
         self.max_torsions = max_torsions
         self.pocket = pocket  # keeps the pocket alive
+        self._destroy = _lib.dock_destroy_ligands
 
     def pair_count(self, lig: int) -> int:
         out = C.c_int32(0)
@@ -173,8 +176,8 @@ class Ligands:
         return out.value
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.dock_destroy_ligands(self.handle)
+        if getattr(self, "handle", None) and getattr(self, "_destroy", None):
+            self._destroy(self.handle)
             self.handle = None
 
 

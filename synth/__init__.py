@@ -289,9 +289,20 @@ def config_ligand_sizes(cfg_id: int, seed: int = 1):
     return atoms.astype(int), tors.astype(int)
 
 
-def config_ligands(cfg_id: int, seed: int = 1, count: int | None = None):
-    """The first ``count`` ligands of a workload recipe (all of them by default)."""
+def _make_ligand_args(args):
+    return make_ligand(*args)
+
+
+def config_ligands(cfg_id: int, seed: int = 1, count: int | None = None, workers: int = 1):
+    """The first ``count`` ligands of a workload recipe (all of them by default).
+    Every ligand has its own seed, so ``workers`` > 1 (a process pool) gives the
+    same ligands."""
     c = CONFIGS[cfg_id]
     atoms, tors = config_ligand_sizes(cfg_id, seed)
     m = len(atoms) if count is None else min(count, len(atoms))
-    return [make_ligand(seed, i, int(atoms[i]), int(tors[i]), c["n_types"]) for i in range(m)]
+    args = [(seed, i, int(atoms[i]), int(tors[i]), c["n_types"]) for i in range(m)]
+    if workers <= 1 or m < 64:
+        return [make_ligand(*a) for a in args]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_make_ligand_args, args, chunksize=64))

@@ -12,6 +12,8 @@
 
 #include "dock.h"
 #include "dock_internal.h"
+#include "maps.h"
+#include "search.h"
 #include "probe.h"
 
 using namespace dock;

@@ -105,65 +105,5 @@ struct ScoreLaunch {
 // Launchers (one translation unit per kernel family).
 hipError_t launch_score(const ScoreLaunch &a, hipStream_t s);
 
-struct DEParams {
-  int32_t pop, n_gen, first_gen;
-  uint64_t seed;
-  float F, CR;
-  double lo[3], hi[3];
-};
-
-hipError_t launch_de_init(const LigandsDev &L, const DEParams &p, int32_t g_stride, float *pop, hipStream_t s);
-hipError_t launch_de_trials(const LigandsDev &L, const DEParams &p, int32_t gen, int32_t g_stride,
-                            const float *pop, float *trials, hipStream_t s);
-hipError_t launch_fill_i32(int32_t *p, int32_t n, int32_t v, hipStream_t s);
-
-// One persistent search launch over the ligands order[0 .. n_order) (one size
-// bucket), taken from the queue counter *queue (which starts at 0).
-struct SearchLaunch {
-  LigandsDev L;
-  MapGeom geom;
-  FFConst ff;
-  MapData maps;
-  DEParams p;
-  int32_t g_stride;
-  int32_t init;
-  float *population;     // [n_ligs][pop][g_stride], in/out
-  float *pop_energy;     // [n_ligs][pop], in/out
-  float *trials;         // [n_ligs][pop][g_stride] scratch
-  float *best_g;         // [n_ligs][g_stride]
-  float *best_e;         // [n_ligs]
-  const float *target;   // [n_ligs] or null
-  int32_t *gen_reached;  // [n_ligs] or null
-  const int32_t *order;
-  int32_t n_order;
-  int32_t *queue;
-  int32_t lds_atoms;     // atom slots per lane in LDS (largest ligand of the launch)
-};
-
-constexpr int kSearchMaxThreads = 256;      // wavefronts per search workgroup: up to 4
-constexpr size_t kLdsPerCU = 160 * 1024;    // gfx950 LDS per compute unit
-
-hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, hipStream_t s, const char **step);
-
-struct MapBuild {
-  MapGeom geom;
-  int32_t n_rec;
-  const float4 *rec;       // x, y, z, charge
-  const int32_t *rec_type;
-  // per (probe type, receptor type): A, B and the 12-10 flag; per type: solpar, vol
-  const float *A, *B;
-  const int32_t *hb;
-  const float *solpar, *vol;
-  float qsolpar, coulomb, e_cap, map_cap, rmin2, h;
-  FFConst ff;
-  float *maps;
-};
-
-hipError_t launch_build_maps(const MapBuild &m, hipStream_t s);
-
-// Derive a packed layout from the linear maps (buffers sized by the caller).
-hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, void *types_out, float4 *ed_out,
-                           hipStream_t s);
-
 }  // namespace dock
 

@@ -4,7 +4,7 @@
 // One thread per grid node; receptor atoms stream through LDS in tiles shared by
 // the 256 threads of a block.  Per-type accumulators live in registers (the
 // loop over types is unrolled to the compile-time maximum and predicated).
-#include "dock_internal.h"
+#include "maps.h"
 
 namespace dock {
 

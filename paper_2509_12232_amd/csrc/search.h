@@ -1,0 +1,47 @@
+// search.h -- launch records of the differential-evolution kernels.
+#pragma once
+#include "dock_internal.h"
+
+namespace dock {
+
+struct DEParams {
+  int32_t pop, n_gen, first_gen;
+  uint64_t seed;
+  float F, CR;
+  double lo[3], hi[3];
+};
+
+hipError_t launch_de_init(const LigandsDev &L, const DEParams &p, int32_t g_stride, float *pop, hipStream_t s);
+hipError_t launch_de_trials(const LigandsDev &L, const DEParams &p, int32_t gen, int32_t g_stride,
+                            const float *pop, float *trials, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t n, int32_t v, hipStream_t s);
+
+// One persistent search launch over the ligands order[0 .. n_order) (one size
+// bucket), taken from the queue counter *queue (which starts at 0).
+struct SearchLaunch {
+  LigandsDev L;
+  MapGeom geom;
+  FFConst ff;
+  MapData maps;
+  DEParams p;
+  int32_t g_stride;
+  int32_t init;
+  float *population;     // [n_ligs][pop][g_stride], in/out
+  float *pop_energy;     // [n_ligs][pop], in/out
+  float *trials;         // [n_ligs][pop][g_stride] scratch
+  float *best_g;         // [n_ligs][g_stride]
+  float *best_e;         // [n_ligs]
+  const float *target;   // [n_ligs] or null
+  int32_t *gen_reached;  // [n_ligs] or null
+  const int32_t *order;
+  int32_t n_order;
+  int32_t *queue;
+  int32_t lds_atoms;     // atom slots per lane in LDS (largest ligand of the launch)
+};
+
+constexpr int kSearchMaxThreads = 256;      // wavefronts per search workgroup: up to 4
+constexpr size_t kLdsPerCU = 160 * 1024;    // gfx950 LDS per compute unit
+
+hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, hipStream_t s, const char **step);
+
+}  // namespace dock

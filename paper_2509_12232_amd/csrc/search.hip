@@ -12,7 +12,7 @@
 // individual, and no other launch or host round trip.
 #include <algorithm>
 
-#include "dock_internal.h"
+#include "search.h"
 #include "philox.h"
 #include "score_pose.h"
 

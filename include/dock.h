@@ -173,6 +173,8 @@ dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs
  * search of Sec. V.  Random draws come from Philox4x64-10 (Salmon et al., SC'11)
  * with key (seed, 0) and counter (individual, generation, ligand, purpose << 32 |
  * block); ligand l of the set uses ligand id l. */
+typedef struct dock_mlp dock_mlp;          /* learned proposal network, on one device */
+
 typedef struct {
   int32_t pop_size;         /* >= 4 */
   int32_t n_generations;    /* >= 0 */
@@ -181,6 +183,18 @@ typedef struct {
   double box_lo[3], box_hi[3];  /* translation bounds (init range and clamp) */
   int32_t init;             /* 1: draw and score the initial population; 0: resume */
   int32_t first_generation; /* absolute index of the first generation this call runs */
+  int32_t stop_at_target;   /* 1: a ligand stops once its population best is <= its target
+                               (needs target and gen_reached); 0: run every generation */
+  /* Learned proposal (not part of the paper's search; NULL = plain DE).  A
+   * proposal round replaces each individual by dock_propose's proposal when the
+   * proposal scores <= the individual (the search's own greedy rule).  Rounds run
+   * right after the initial population (init = 1) and then before generation g
+   * for every g = first_generation + k * proposal_every (k >= 1, proposal_every
+   * > 0) with g < proposal_until. */
+  const dock_mlp *proposal;
+  float proposal_step;      /* alpha_max of dock_propose, > 0 */
+  int32_t proposal_every;   /* >= 0 (0: only the round after the initial population) */
+  int32_t proposal_until;   /* generation bound of the later rounds */
 } dock_search_params;
 
 /* Initial population: rows [n_ligands][pop_size][g_stride] on device, genes
@@ -212,6 +226,84 @@ dock_status dock_de_trials(const dock_ligands *ligs, const dock_search_params *p
 dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, const dock_search_params *params,
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);
+
+/* ---- Learned proposal --------------------------------------------------------
+ * An addition to the paper's method (whose search, Sec. V, has no learned
+ * part): a perceptron 96 -> 256 -> 256 -> 32 with ReLU hidden layers proposes
+ * genotype moves; every proposal is scored by the exact function and kept only
+ * by the search's greedy rule, so plain DE remains the judge.  Matrix products
+ * run on the matrix cores with bfloat16 operands (inputs, weights, hidden
+ * activations and back-propagated errors rounded to nearest-even bfloat16) and
+ * float32 accumulation; everything else is float32.
+ *
+ * Network input of an individual (96 features): 32 encoded genes -- (t_d - c_d) /
+ * h_d for the box centre c and half-width h (0 where h = 0), the unit quaternion
+ * with w >= 0 (identity for |q|^2 < 1e-24), theta_k / pi for k < min(n_torsions,
+ * 25), zeros -- then the ligand's 64 descriptor features.  Output (32): a move
+ * in the same encoding.
+ *
+ * Parameters, packed float32 (DOCK_MLP_PARAMS values): W1 [96][256] (input
+ * major), b1 [256], W2 [256][256], b2 [256], W3 [256][32], b3 [32]; layer l
+ * computes a_l = relu(a_{l-1} W_l + b_l), the last without relu. */
+#define DOCK_MLP_IN 96
+#define DOCK_MLP_HIDDEN 256
+#define DOCK_MLP_OUT 32
+#define DOCK_MLP_PARAMS 98848
+#define DOCK_DESC 64
+#define DOCK_MLP_MAX_BATCH 65536
+
+/* New network on a device: He-uniform weights from seed (U(+-sqrt(6 / fan_in)),
+ * the last layer scaled by 0.1), zero biases, zero Adam state. */
+dock_status dock_mlp_create(int32_t device, uint64_t seed, dock_mlp **out);
+dock_status dock_mlp_destroy(dock_mlp *net);
+/* Replace the parameters (host float[DOCK_MLP_PARAMS], finite) and reset the
+ * Adam state; synchronous. */
+dock_status dock_mlp_set_params(dock_mlp *net, const float *params);
+/* Copy the parameters out (host float[DOCK_MLP_PARAMS]); synchronous. */
+dock_status dock_mlp_get_params(const dock_mlp *net, float *params);
+/* y [n][32] = network(x [n][96]) (both device float32), n >= 0. */
+dock_status dock_mlp_forward(const dock_mlp *net, const float *x, int64_t n, float *y, void *stream);
+/* Loss (1/n) sum_i w_i sum_j (y_ij - target_ij)^2 of rows x [n][96] against
+ * target [n][32] with weights w [n] (NULL = 1), and its gradients by
+ * back-propagation: grads (device float[DOCK_MLP_PARAMS], packed like the
+ * parameters) and loss (device float[1]).  1 <= n <= DOCK_MLP_MAX_BATCH.  Uses
+ * the network's training workspace: calls on one network must not overlap. */
+dock_status dock_mlp_gradients(dock_mlp *net, const float *x, const float *target, const float *weight, int32_t n,
+                               float *grads, float *loss, void *stream);
+/* n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * minibatches of `batch` consecutive rows: step s uses rows starting at
+ * (s * batch) mod n_rows.  n_rows must be a multiple of batch, 1 <= batch <=
+ * DOCK_MLP_MAX_BATCH.  losses (device float[n_steps], may be NULL) receives each
+ * step's loss before its update.  Calls on one network must not overlap. */
+dock_status dock_mlp_train(dock_mlp *net, const float *x, const float *target, const float *weight, int64_t n_rows,
+                           int32_t batch, int32_t n_steps, float lr, float *losses, void *stream);
+
+/* Descriptor of every ligand, out [n_ligands][64] (device float32): [0, 32) the
+ * fraction of its atoms of each type; 32 torsions / 20; 33 atoms / 96; 34 mean
+ * |charge|; 35 mean charge; 36 radius of gyration / 10 A; 37 intra pairs / 4096;
+ * the rest 0. */
+dock_status dock_ligand_descriptors(const dock_ligands *ligs, float *out, void *stream);
+
+/* Network inputs x [n_ligands * pop_size][96] (device) of a population
+ * [n_ligands][pop_size][g_stride] (device); params supplies pop_size and the box. */
+dock_status dock_mlp_features(const dock_ligands *ligs, const dock_search_params *params, int32_t g_stride,
+                              const float *population, float *x, void *stream);
+
+/* Encoded moves out [n_ligands * pop_size][32] (device) from population `from` to
+ * population `to` (same shape): (t_to - t_from) / h; q_to' - q_from' for the
+ * canonical unit quaternions with q_to' of the sign nearer q_from';
+ * wrap(theta_to - theta_from) / pi for the first min(n_torsions, 25); zeros. */
+dock_status dock_mlp_moves(const dock_ligands *ligs, const dock_search_params *params, int32_t g_stride,
+                           const float *from, const float *to, float *out, void *stream);
+
+/* Proposals (same shape as population, device): for individual i of ligand l,
+ * y = network(features), alpha = alpha_max (1 - u) with u the first uniform of
+ * the Philox stream (i, generation, l, purpose 4) (so alpha in (0, alpha_max]),
+ * then t + alpha h y_t clamped to the box; canonical q + alpha y_q; wrap(theta_k +
+ * alpha pi y_k) for k < min(n_torsions, 25); other genes copied. */
+dock_status dock_propose(const dock_ligands *ligs, const dock_mlp *net, const dock_search_params *params,
+                         int32_t generation, float alpha_max, int32_t g_stride, const float *population,
+                         float *proposals, void *stream);
 
 /* ---- Roofline probes: measurement aids, not steps of the docking path. ---- */
 

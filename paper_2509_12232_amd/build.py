@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdock.so")
-SOURCES = ["api.hip", "score.hip", "search.hip", "maps.hip", "probe.hip"]
+SOURCES = ["api.hip", "api_learn.hip", "score.hip", "search.hip", "maps.hip", "probe.hip", "learn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -10,8 +10,7 @@
 #include <numeric>
 #include <vector>
 
-#include "dock.h"
-#include "dock_internal.h"
+#include "api_internal.h"
 #include "maps.h"
 #include "search.h"
 #include "probe.h"
@@ -21,7 +20,7 @@ using namespace dock;
 // ------------------------------------------------------------------------------ errors
 static thread_local char g_err[512];
 
-static dock_status set_err(dock_status st, const char *fmt, ...) {
+dock_status set_err(dock_status st, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof g_err, fmt, ap);
@@ -29,73 +28,15 @@ static dock_status set_err(dock_status st, const char *fmt, ...) {
   return st;
 }
 
-static dock_status hip_err(hipError_t e, const char *what) {
+dock_status hip_err(hipError_t e, const char *what) {
   if (e == hipErrorOutOfMemory) return set_err(DOCK_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
   return set_err(DOCK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                  \
-  do {                                       \
-    hipError_t e_ = (expr);                  \
-    if (e_ != hipSuccess) return hip_err(e_, what); \
-  } while (0)
-
 extern "C" const char *dock_last_error(void) { return g_err; }
 extern "C" int32_t dock_version(void) { return 1; }
 
-namespace {
-
-// Makes `device` current for the scope of an API call.
-struct DeviceScope {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceScope(int device) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != device) err = hipSetDevice(device);
-  }
-  ~DeviceScope() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-template <class T>
-hipError_t upload(T **dst, const std::vector<T> &src) {
-  *dst = nullptr;
-  if (src.empty()) return hipMalloc((void **)dst, sizeof(T));  // keep a valid pointer
-  hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
-  if (e != hipSuccess) return e;
-  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
-}
-
-}  // namespace
-
 // ------------------------------------------------------------------------------ handles
-struct dock_pocket {
-  int device = 0;
-  MapGeom geom{};
-  FFConst ffc{};
-  int n_types = 0;
-  std::vector<float> Rii, epsii, vol, solpar;
-  std::vector<uint8_t> hbond;
-  float coulomb = 0, qsolpar = 0;
-  float *maps = nullptr;      // ABI layout
-  int64_t plane = 0;
-  int32_t layout = kLinear;    // layout the scoring kernel reads
-  int32_t n_cu = 1;            // compute units of the device (persistent launch size)
-  void *tpack = nullptr;       // packed type maps
-  float4 *edpack = nullptr;    // packed electrostatic/desolvation records
-  int64_t t_stride = 0;
-  MapData view() const {
-    MapData m{};
-    m.lin = maps;
-    m.t_stride = t_stride;
-    if (layout == kZPair) m.tz = (const float2 *)tpack, m.edz = edpack;
-    if (layout == kYZQuad) m.tq = (const float4 *)tpack, m.edq = edpack;
-    return m;
-  }
-};
-
 // Packed layout for the scoring kernel: the yz-quad layout (4x the type maps,
 // the fewest cache lines per lookup) while its copy stays within kQuadBudget
 // bytes, so that it remains resident in the 256 MB Infinity Cache; else the
@@ -136,42 +77,6 @@ static void free_pocket(dock_pocket *p) {
     if (q) (void)hipFree(q);
   delete p;
 }
-
-// Ligands with (previous bucket's upper, upper] atoms: order[offset .. offset + count).
-struct LigandBucket {
-  int32_t upper;      // atom-count bound of the bucket
-  int32_t lds_atoms;  // largest ligand actually in it (sizes the LDS of its launch)
-  int32_t offset, count;
-};
-
-struct dock_ligands {
-  int device = 0;
-  int n_ligs = 0;
-  int max_atoms = 0, max_tors = 0;
-  std::vector<LigHeader> hdr_host;
-  std::vector<int32_t> pair_count;
-  LigHeader *hdr = nullptr;
-  float4 *atoms = nullptr;
-  int32_t *atom_type = nullptr;
-  TorRec *tors = nullptr;
-  PairRec *pairs = nullptr;
-  // ligands grouped by atom count; within a group, costliest first
-  std::vector<LigandBucket> buckets;
-  int32_t *order = nullptr;
-  // side streams for concurrent bucket launches (created on first use)
-  mutable std::mutex side_mu;
-  mutable std::vector<hipStream_t> side;
-  hipError_t ensure_side_streams() const {
-    while (side.size() < 4) {
-      hipStream_t st = nullptr;
-      hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-      if (e != hipSuccess) return e;
-      side.push_back(st);
-    }
-    return hipSuccess;
-  }
-  LigandsDev view() const { return LigandsDev{hdr, atoms, atom_type, tors, pairs, n_ligs}; }
-};
 
 // ------------------------------------------------------------------------------ pockets
 static dock_status check_ff(const dock_forcefield *ff) {
@@ -387,6 +292,7 @@ struct PrepOut {
   std::vector<TorRec> tors;
   std::vector<PairRec> pairs;  // 12-6 groups, two spare zero groups, then 12-10 pairs
   int n_plain = 0, n_hb = 0, n_groups = 0;
+  float desc[64];  // descriptor features of the learned proposal
 };
 
 // Root at atom 0; depth-first pre-order renumbering so each rotatable bond's far
@@ -523,6 +429,26 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
   o.pairs = plain;
   o.pairs.resize((size_t)4 * (o.n_groups + 2), PairRec{0, 0.f, 0.f, 0.f, 0.f});
   o.pairs.insert(o.pairs.end(), hb.begin(), hb.end());
+  // descriptor: type fractions, torsion and atom counts, charge statistics,
+  // radius of gyration of the reference conformation, pair count
+  double f[64] = {0};
+  double rg2 = 0, qa = 0, qs = 0;
+  for (int i = 0; i < n; ++i) {
+    f[d.type[i]] += 1.0 / n;
+    qa += fabs((double)d.charge[i]);
+    qs += d.charge[i];
+    for (int k = 0; k < 3; ++k) {
+      const double x = d.xyz[3 * i + k] - c[k];
+      rg2 += x * x;
+    }
+  }
+  f[32] = nt / 20.0;
+  f[33] = n / 96.0;
+  f[34] = qa / n;
+  f[35] = qs / n;
+  f[36] = sqrt(rg2 / n) / 10.0;
+  f[37] = (o.n_plain + o.n_hb) / 4096.0;
+  for (int j = 0; j < 64; ++j) o.desc[j] = (float)f[j];
   return DOCK_OK;
 }
 
@@ -531,7 +457,7 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
 static void free_ligands(dock_ligands *L) {
   for (hipStream_t st : L->side) (void)hipStreamDestroy(st);
   for (void *q : {(void *)L->hdr, (void *)L->atoms, (void *)L->atom_type, (void *)L->tors, (void *)L->pairs,
-                  (void *)L->order})
+                  (void *)L->order, (void *)L->desc})
     if (q) (void)hipFree(q);
   delete L;
 }
@@ -548,6 +474,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   std::vector<int32_t> types;
   std::vector<TorRec> tors;
   std::vector<PairRec> pairs;
+  std::vector<float> desc;
   int max_atoms = 1, max_tors = 0;
   PrepOut o;
   for (int l = 0; l < n_ligands; ++l) {
@@ -568,6 +495,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
     types.insert(types.end(), o.types.begin(), o.types.end());
     tors.insert(tors.end(), o.tors.begin(), o.tors.end());
     pairs.insert(pairs.end(), o.pairs.begin(), o.pairs.end());
+    desc.insert(desc.end(), o.desc, o.desc + 64);
     max_atoms = std::max(max_atoms, h.n_atoms);
     max_tors = std::max(max_tors, h.n_tors);
   }
@@ -603,6 +531,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   if (e == hipSuccess) e = upload(&L->tors, tors);
   if (e == hipSuccess) e = upload(&L->pairs, pairs);
   if (e == hipSuccess) e = upload(&L->order, order);
+  if (e == hipSuccess) e = upload(&L->desc, desc);
   if (e != hipSuccess) {
     free_ligands(L);
     return hip_err(e, "ligand upload");
@@ -718,6 +647,73 @@ extern "C" dock_status dock_de_trials(const dock_ligands *L, const dock_search_p
   return DOCK_OK;
 }
 
+// One pass of the persistent search kernels over every size bucket, generations
+// [S.p.first_gen, S.p.first_gen + S.p.n_gen): the buckets run concurrently on the
+// handle's side streams (forked from and joined back to s), so that small
+// buckets do not leave the GPU idle while the last ligands of another finish.
+static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, SearchLaunch S, int32_t *queues,
+                              hipStream_t s, const char **step) {
+  const int nb = (int)L->buckets.size();
+  *step = "queue reset";
+  hipError_t e = launch_fill_i32(queues, nb, 0, s);
+  std::lock_guard<std::mutex> guard(L->side_mu);
+  if (e == hipSuccess) *step = "side streams", e = L->ensure_side_streams();
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, s);
+  int k = 0;
+  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+    const LigandBucket &B = L->buckets[b];
+    if (B.count == 0) continue;
+    hipStream_t side = L->side[k++ % L->side.size()];
+    *step = "side streams";
+    e = hipStreamWaitEvent(side, fork, 0);
+    S.order = L->order + B.offset;
+    S.n_order = B.count;
+    S.queue = queues + b;
+    S.lds_atoms = B.lds_atoms;
+    if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, side, step);
+    hipEvent_t done = nullptr;
+    if (e == hipSuccess) *step = "side streams", e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e == hipSuccess) {
+      joins.push_back(done);
+      e = hipEventRecord(done, side);
+    }
+  }
+  for (hipEvent_t ev : joins) {
+    hipError_t w = hipStreamWaitEvent(s, ev, 0);
+    if (e == hipSuccess) e = w;
+    (void)hipEventDestroy(ev);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  return e;
+}
+
+// Scores of a whole population [n_ligs][pop][g_stride] into energies [n_ligs][pop].
+static hipError_t score_population(const dock_pocket *p, const dock_ligands *L, int32_t pop, int32_t g_stride,
+                                   const float *genotypes, float *energies, hipStream_t s) {
+  ScoreLaunch a = make_score(p, L);
+  a.poses_per_ligand = pop;
+  a.genotypes = genotypes;
+  a.g_stride = g_stride;
+  a.n_poses = (int64_t)L->n_ligs * pop;
+  a.energies = energies;
+  return launch_score(a, s);
+}
+
+// A learned-proposal round before generation gen: proposals of the population,
+// their exact scores, greedy replacement.
+static hipError_t proposal_round(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                 const PopRows &R, int32_t gen, float *pop, float *pop_e, float *prop, float *prop_e,
+                                 const int32_t *gen_reached, int32_t stop, hipStream_t s, const char **step) {
+  *step = "proposals";
+  hipError_t e = run_proposals(q->proposal, R, q->proposal_step, q->seed, gen, pop, prop, s);
+  if (e == hipSuccess) *step = "proposal scores", e = score_population(p, L, R.pop, R.g_stride, prop, prop_e, s);
+  if (e == hipSuccess) *step = "proposal selection", e = launch_select(R, prop, prop_e, pop, pop_e, gen_reached, stop, s);
+  return e;
+}
+
 extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
                                    int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                                    float *best_energies, const float *target, int32_t *gen_reached, void *stream) {
@@ -728,6 +724,15 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
     return set_err(DOCK_E_INVALID, "null output buffer");
   if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
   if ((int64_t)q->first_generation + q->n_generations > 0x7fffffff) return set_err(DOCK_E_INVALID, "too many generations");
+  const bool track = target && gen_reached;
+  if (q->stop_at_target && !track) return set_err(DOCK_E_INVALID, "stop_at_target needs target and gen_reached");
+  const dock_mlp *net = q->proposal;
+  if (net) {
+    if (mlp_device(net) != p->device) return set_err(DOCK_E_INVALID, "proposal network on another device");
+    if (!(q->proposal_step > 0) || !isfinite(q->proposal_step))
+      return set_err(DOCK_E_INVALID, "proposal_step must be positive and finite");
+    if (q->proposal_every < 0) return set_err(DOCK_E_INVALID, "proposal_every must be >= 0");
+  }
   DeviceScope ds(p->device);
   HIP_TRY(ds.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -745,49 +750,50 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   S.pop_energy = pop_energy;
   S.best_g = best_genotypes;
   S.best_e = best_energies;
-  S.target = (target && gen_reached) ? target : nullptr;
-  S.gen_reached = (target && gen_reached) ? gen_reached : nullptr;
-  const int nb = (int)L->buckets.size();
+  S.target = track ? target : nullptr;
+  S.gen_reached = track ? gen_reached : nullptr;
+  S.stop = q->stop_at_target ? 1 : 0;
   int32_t *queues = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s), "trial buffer");
-  hipError_t e = hipMallocAsync((void **)&queues, sizeof(int32_t) * nb, s);
-  if (e == hipSuccess) e = launch_fill_i32(queues, nb, 0, s);
-  // The size buckets run concurrently on the handle's side streams (forked from
-  // and joined back to the caller's stream), so that small buckets do not leave
-  // the GPU idle while the last ligands of another bucket finish.
-  std::lock_guard<std::mutex> guard(L->side_mu);
-  if (e == hipSuccess) e = L->ensure_side_streams();
-  hipEvent_t fork = nullptr;
-  std::vector<hipEvent_t> joins;
-  const char *step = "side streams";
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(fork, s);
-  int k = 0;
-  for (int b = 0; b < nb && e == hipSuccess; ++b) {
-    const LigandBucket &B = L->buckets[b];
-    if (B.count == 0) continue;
-    hipStream_t side = L->side[k++ % L->side.size()];
-    e = hipStreamWaitEvent(side, fork, 0);
-    S.order = L->order + B.offset;
-    S.n_order = B.count;
-    S.queue = queues + b;
-    S.lds_atoms = B.lds_atoms;
-    if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, side, &step);
-    hipEvent_t done = nullptr;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-    if (e == hipSuccess) {
-      joins.push_back(done);
-      e = hipEventRecord(done, side);
+  float *prop_e = nullptr;
+  const char *step = "search buffers";
+  hipError_t e = hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&queues, sizeof(int32_t) * L->buckets.size(), s);
+  if (e == hipSuccess && net) e = hipMallocAsync((void **)&prop_e, sizeof(float) * n, s);
+  if (e == hipSuccess && !net) {
+    e = search_pass(p, L, S, queues, s, &step);
+  } else if (e == hipSuccess) {
+    // Learned proposals: the trial buffer holds the proposals of a round; the
+    // generations between rounds run as plain persistent passes that resume.
+    const PopRows R = make_pop_rows(L, P, g_stride, q->box_lo, q->box_hi);
+    const int g0 = q->first_generation, g_end = g0 + q->n_generations;
+    if (q->init) {
+      step = "initial population";
+      e = launch_de_init(L->view(), S.p, g_stride, population, s);
+      if (e == hipSuccess) e = score_population(p, L, P, g_stride, population, pop_energy, s);
+      if (e == hipSuccess && track) e = launch_fill_i32(gen_reached, nl, -1, s);
+      if (e == hipSuccess)
+        e = proposal_round(p, L, q, R, g0, population, pop_energy, S.trials, prop_e, S.gen_reached, S.stop, s, &step);
     }
+    int g = g0;
+    do {
+      int seg_end = g_end;
+      if (q->proposal_every > 0) {
+        const int64_t nb = g0 + ((int64_t)(g - g0) / q->proposal_every + 1) * q->proposal_every;
+        if (nb < q->proposal_until && nb < g_end) seg_end = (int)nb;
+      }
+      SearchLaunch T = S;
+      T.init = 0;
+      T.p.first_gen = g;
+      T.p.n_gen = seg_end - g;
+      if (e == hipSuccess) e = search_pass(p, L, T, queues, s, &step);
+      g = seg_end;
+      if (e == hipSuccess && g < g_end)
+        e = proposal_round(p, L, q, R, g, population, pop_energy, S.trials, prop_e, S.gen_reached, S.stop, s, &step);
+    } while (g < g_end && e == hipSuccess);
   }
-  for (hipEvent_t ev : joins) {
-    hipError_t w = hipStreamWaitEvent(s, ev, 0);
-    if (e == hipSuccess) e = w;
-    (void)hipEventDestroy(ev);
-  }
-  if (fork) (void)hipEventDestroy(fork);
+  if (prop_e) (void)hipFreeAsync(prop_e, s);
   if (queues) (void)hipFreeAsync(queues, s);
-  (void)hipFreeAsync(S.trials, s);
+  if (S.trials) (void)hipFreeAsync(S.trials, s);
   if (e != hipSuccess) return hip_err(e, step);
   return DOCK_OK;
 }

@@ -1,0 +1,474 @@
+// learn.hip -- the learned proposal on gfx950: a 96-256-256-32 perceptron whose
+// products run on the matrix cores (v_mfma_f32_32x32x16_bf16: bfloat16 operands,
+// float32 accumulation), its training step (squared-error loss,
+// back-propagation, Adam) and the kernels that turn genotypes into network
+// inputs and network outputs into proposal genotypes.
+//
+// Every product is one wavefront per 32x32 output tile.  Operands are kept in
+// HBM in layouts where each lane's eight bfloat16 values of a fragment are one
+// 16-byte load: activations row-major (reduction index contiguous) for the
+// forward and error products, and eight-row interleaved ("p8") copies for the
+// weight-gradient products, whose reduction index is the row.
+#include <math.h>
+
+#include "learn.h"
+#include "philox.h"
+
+namespace dock {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bf16x8 frag(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Lane l of a 32x32 accumulator holds column l % 32 and rows
+// 8 (r / 4) + 4 (l / 32) + r % 4 of its registers r = 0..15.
+__device__ __forceinline__ int acc_row(int r, int l) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+
+__device__ __forceinline__ int64_t p8_index(int64_t row, int cols, int col) {
+  return (((row >> 3) * cols + col) << 3) + (row & 7);
+}
+
+// ------------------------------------------------------------------- products
+enum { kEpiRelu = 0, kEpiOut = 1, kEpiMask = 2 };
+
+// D[mp][N] = A[mp][K] * B, with B given as Bt[N][K]; epilogue by EPI:
+//   kEpiRelu: bfloat16(max(D + bias, 0))   -> out (+ out_p8)
+//   kEpiOut:  D + bias                      -> out_f32
+//   kEpiMask: bfloat16(D where mask > 0)    -> out (+ out_p8)
+struct GemmRK {
+  const bf16 *A;
+  const bf16 *Bt;
+  int64_t mp;
+  int32_t N, K;
+  const float *bias;
+  const bf16 *mask;
+  bf16 *out;
+  bf16 *out_p8;
+  float *out_f32;
+  int32_t waves_n;  // wavefronts of a block along N (1, 2 or 4)
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_rk_kernel(GemmRK g) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wm = 4 / g.waves_n;
+  const int64_t tm = (int64_t)blockIdx.x * wm + wave / g.waves_n;
+  const int tn = blockIdx.y * g.waves_n + wave % g.waves_n;
+  if (tm * kMlpRowTile >= g.mp || tn * 32 >= g.N) return;
+  const bf16 *a = g.A + (tm * kMlpRowTile + (l & 31)) * g.K + 8 * (l >> 5);
+  const bf16 *b = g.Bt + (int64_t)(tn * 32 + (l & 31)) * g.K + 8 * (l >> 5);
+  f32x16 acc = {};
+  for (int k = 0; k < g.K; k += 16) acc = mfma(frag(a + k), frag(b + k), acc);
+  const int col = tn * 32 + (l & 31);
+  const float bias = EPI == kEpiMask ? 0.f : g.bias[col];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = tm * kMlpRowTile + acc_row(r, l);
+    float v = acc[r] + bias;
+    if (EPI == kEpiOut) {
+      g.out_f32[row * g.N + col] = v;
+      continue;
+    }
+    if (EPI == kEpiRelu) v = v > 0.f ? v : 0.f;
+    if (EPI == kEpiMask) v = (float)g.mask[row * g.N + col] > 0.f ? v : 0.f;
+    const bf16 h = (bf16)v;
+    g.out[row * g.N + col] = h;
+    if (g.out_p8) g.out_p8[p8_index(row, g.N, col)] = h;
+  }
+}
+
+// partial[c][K][N] = sum over rows m of chunk c of X[m][k] Z[m][n], from the p8
+// copies of X [mp][K] and Z [mp][N].
+struct GemmWG {
+  const bf16 *Xp8;
+  const bf16 *Zp8;
+  int64_t mp;
+  int32_t K, N;
+  float *partial;
+};
+
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(GemmWG g) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tiles_n = g.N / 32;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= (g.K / 32) * tiles_n) return;
+  const int ti = tile / tiles_n, tn = tile % tiles_n;
+  const int64_t m0 = (int64_t)blockIdx.y * kWgradChunk;
+  const int64_t m1 = m0 + kWgradChunk < g.mp ? m0 + kWgradChunk : g.mp;
+  f32x16 acc = {};
+  for (int64_t m = m0; m < m1; m += 16) {
+    const int64_t blk = (m >> 3) + (l >> 5);
+    acc = mfma(frag(g.Xp8 + ((blk * g.K + ti * 32 + (l & 31)) << 3)),
+               frag(g.Zp8 + ((blk * g.N + tn * 32 + (l & 31)) << 3)), acc);
+  }
+  float *out = g.partial + (int64_t)blockIdx.y * g.K * g.N;
+  const int col = tn * 32 + (l & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[(ti * 32 + acc_row(r, l)) * g.N + col] = acc[r];
+}
+
+// out[i] = sum_c partial[c][i], in chunk order
+__global__ void reduce_partial_kernel(const float *partial, int chunks, int n, float *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * n + i];
+  out[i] = s;
+}
+
+// out[c] = sum over rows of Z[m][c] (row order)
+__global__ void colsum_kernel(const bf16 *Z, int64_t mp, int N, float *out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  float s = 0.f;
+  for (int64_t m = 0; m < mp; ++m) s += (float)Z[m * N + c];
+  out[c] = s;
+}
+
+// ------------------------------------------------------------ input, loss, Adam
+__global__ void mlp_input_kernel(const float *x, int64_t m, int64_t mp, bf16 *a0, bf16 *a0p8) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mp * kMlpIn) return;
+  const int64_t row = i / kMlpIn;
+  const int c = (int)(i % kMlpIn);
+  const bf16 h = (bf16)(row < m ? x[i] : 0.f);
+  a0[i] = h;
+  if (a0p8) a0p8[p8_index(row, kMlpIn, c)] = h;
+}
+
+// g = bfloat16((2 / m) w (y - t)) for valid rows, 0 for padding rows; per-block
+// sums of w (y - t)^2 (fixed tree order).
+__global__ __launch_bounds__(256) void mlp_loss_kernel(const float *y, const float *t, const float *w, int64_t m,
+                                                       int64_t mp, float scale, bf16 *g, bf16 *gp8, float *part) {
+  __shared__ float sh[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float sq = 0.f;
+  if (i < mp * kMlpOut) {
+    const int64_t row = i / kMlpOut;
+    const int c = (int)(i % kMlpOut);
+    float d = 0.f;
+    if (row < m) {
+      const float wr = w ? w[row] : 1.f;
+      const float e = y[i] - t[row * kMlpOut + c];
+      sq = wr * e * e;
+      d = scale * wr * e;
+    }
+    const bf16 h = (bf16)d;
+    g[i] = h;
+    gp8[p8_index(row, kMlpOut, c)] = h;
+  }
+  sh[threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void ordered_sum_kernel(const float *part, int n, float scale, float *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float s = 0.f;
+  for (int i = 0; i < n; ++i) s += part[i];
+  out[0] = s * scale;
+}
+
+// bfloat16 copies of weight element e of the packed vector (e < kOffW3 + 256 * 32,
+// biases excluded by the caller).
+__device__ __forceinline__ void store_weight_copies(int e, float v, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2,
+                                                    bf16 *wr3) {
+  const bf16 h = (bf16)v;
+  if (e < kOffB1) {
+    const int k = e / kMlpHidden, n = e % kMlpHidden;
+    wt1[n * kMlpIn + k] = h;
+  } else if (e >= kOffW2 && e < kOffB2) {
+    const int o = e - kOffW2, k = o / kMlpHidden, n = o % kMlpHidden;
+    wt2[n * kMlpHidden + k] = h;
+    wr2[k * kMlpHidden + n] = h;
+  } else if (e >= kOffW3 && e < kOffB3) {
+    const int o = e - kOffW3, k = o / kMlpOut, n = o % kMlpOut;
+    wt3[n * kMlpHidden + k] = h;
+    wr3[k * kMlpOut + n] = h;
+  }
+}
+
+__global__ void mlp_refresh_kernel(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kMlpParams) return;
+  store_weight_copies(e, master[e], wt1, wt2, wt3, wr2, wr3);
+}
+
+// Adam (Kingma & Ba, ICLR 2015) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void mlp_adam_kernel(float *p, float *m, float *v, const float *grads, AdamStep a, bf16 *wt1, bf16 *wt2,
+                                bf16 *wt3, bf16 *wr2, bf16 *wr3) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kMlpParams) return;
+  const float g = grads[e];
+  const float mm = a.beta1 * m[e] + (1.f - a.beta1) * g;
+  const float vv = a.beta2 * v[e] + (1.f - a.beta2) * g * g;
+  m[e] = mm;
+  v[e] = vv;
+  const float w = p[e] - a.lr * (mm / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+  p[e] = w;
+  store_weight_copies(e, w, wt1, wt2, wt3, wr2, wr3);
+}
+
+// ------------------------------------------------------------------ genotypes
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr float kTwoPiF = 6.28318530717958647692f;
+
+__device__ __forceinline__ float wrapf(float a) {
+  a = fmodf(a, kTwoPiF);
+  if (a > kPiF) a -= kTwoPiF;
+  else if (a <= -kPiF) a += kTwoPiF;
+  return a;
+}
+
+// unit quaternion with w >= 0; identity for a zero quaternion
+__device__ __forceinline__ void canonical_q(const float *g, float q[4]) {
+  const float nn = g[3] * g[3] + g[4] * g[4] + g[5] * g[5] + g[6] * g[6];
+  if (nn < 1e-24f) {
+    q[0] = 1.f, q[1] = q[2] = q[3] = 0.f;
+    return;
+  }
+  float s = 1.f / sqrtf(nn);
+  if (g[3] < 0.f) s = -s;
+  for (int c = 0; c < 4; ++c) q[c] = g[3 + c] * s;
+}
+
+__device__ __forceinline__ void box_half(const PopRows &R, int d, float &c, float &h) {
+  c = 0.5f * (R.lo[d] + R.hi[d]);
+  h = 0.5f * (R.hi[d] - R.lo[d]);
+}
+
+// Network input of one genotype row: 32 encoded genes, then the ligand's 64
+// descriptor features.
+__device__ void encode_row(const PopRows &R, int64_t r, const float *genotypes, float f[kMlpIn]) {
+  const int lig = (int)(r / R.pop);
+  const float *g = genotypes + r * R.g_stride;
+  const int nt = min(R.hdr[lig].n_tors, kEncTorsions);
+  for (int d = 0; d < 3; ++d) {
+    float c, h;
+    box_half(R, d, c, h);
+    f[d] = h > 0.f ? (g[d] - c) / h : 0.f;
+  }
+  float q[4];
+  canonical_q(g, q);
+  for (int c = 0; c < 4; ++c) f[3 + c] = q[c];
+  for (int k = 0; k < kEncTorsions; ++k) f[7 + k] = k < nt ? g[7 + k] / kPiF : 0.f;
+  const float *ds = R.desc + (int64_t)lig * kDesc;
+  for (int j = 0; j < kDesc; ++j) f[kEncGenes + j] = ds[j];
+}
+
+__global__ void encode_kernel(PopRows R, int64_t row0, int64_t n, const float *genotypes, float *x, bf16 *a0,
+                              int64_t a0_rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = a0 ? a0_rows : n;
+  if (i >= rows) return;
+  float f[kMlpIn];
+  if (i < n) {
+    encode_row(R, row0 + i, genotypes, f);
+  } else {
+    for (int j = 0; j < kMlpIn; ++j) f[j] = 0.f;
+  }
+  if (a0) {
+    bf16 *o = a0 + i * kMlpIn;
+    for (int j = 0; j < kMlpIn; ++j) o[j] = (bf16)f[j];
+  } else {
+    float *o = x + i * kMlpIn;
+    for (int j = 0; j < kMlpIn; ++j) o[j] = f[j];
+  }
+}
+
+__global__ void moves_kernel(PopRows R, const float *from, const float *to, float *out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.n_rows) return;
+  const int lig = (int)(r / R.pop);
+  const float *a = from + r * R.g_stride, *b = to + r * R.g_stride;
+  float *o = out + r * kMlpOut;
+  const int nt = min(R.hdr[lig].n_tors, kEncTorsions);
+  for (int d = 0; d < 3; ++d) {
+    float c, h;
+    box_half(R, d, c, h);
+    o[d] = h > 0.f ? (b[d] - a[d]) / h : 0.f;
+  }
+  float qa[4], qb[4];
+  canonical_q(a, qa);
+  canonical_q(b, qb);
+  const float dot = qa[0] * qb[0] + qa[1] * qb[1] + qa[2] * qb[2] + qa[3] * qb[3];
+  const float sgn = dot < 0.f ? -1.f : 1.f;
+  for (int c = 0; c < 4; ++c) o[3 + c] = sgn * qb[c] - qa[c];
+  for (int k = 0; k < kEncTorsions; ++k) o[7 + k] = k < nt ? wrapf(b[7 + k] - a[7 + k]) / kPiF : 0.f;
+}
+
+__global__ void decode_kernel(PopRows R, int64_t row0, int64_t n, const float *genotypes, const float *y,
+                              float alpha_max, uint64_t seed, int32_t generation, float *prop) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = row0 + i;
+  const int lig = (int)(r / R.pop), ind = (int)(r % R.pop);
+  const float *g = genotypes + r * R.g_stride;
+  const float *yy = y + i * kMlpOut;
+  float *o = prop + r * R.g_stride;
+  DrawStream s(seed, (uint64_t)ind, (uint64_t)generation, (uint64_t)lig, kPurposeProposal);
+  const float alpha = alpha_max * (float)(1.0 - s.unit());
+  for (int j = 0; j < R.g_stride; ++j) o[j] = g[j];
+  for (int d = 0; d < 3; ++d) {
+    float c, h;
+    box_half(R, d, c, h);
+    const float v = g[d] + alpha * h * yy[d];
+    o[d] = fminf(fmaxf(v, R.lo[d]), R.hi[d]);
+  }
+  float q[4];
+  canonical_q(g, q);
+  for (int c = 0; c < 4; ++c) o[3 + c] = q[c] + alpha * yy[3 + c];
+  const int nt = min(R.hdr[lig].n_tors, kEncTorsions);
+  for (int k = 0; k < nt; ++k) o[7 + k] = wrapf(g[7 + k] + alpha * kPiF * yy[7 + k]);
+}
+
+__global__ void select_kernel(PopRows R, const float *prop, const float *prop_e, float *pop, float *pop_e,
+                              const int32_t *gen_reached, int32_t skip_reached) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.n_rows) return;
+  const int lig = (int)(r / R.pop);
+  if (skip_reached && gen_reached && gen_reached[lig] >= 0) return;
+  const float e = prop_e[r];
+  if (!(e <= pop_e[r])) return;
+  pop_e[r] = e;
+  for (int j = 0; j < R.g_stride; ++j) pop[r * R.g_stride + j] = prop[r * R.g_stride + j];
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int EPI>
+static hipError_t gemm_rk(const GemmRK &g, hipStream_t s) {
+  GemmRK a = g;
+  a.waves_n = a.N >= 128 ? 4 : a.N >= 64 ? 2 : 1;
+  const int wm = 4 / a.waves_n;
+  const int64_t tiles_m = a.mp / kMlpRowTile;
+  dim3 grid(blocks_for(tiles_m, wm), (unsigned)((a.N / 32 + a.waves_n - 1) / a.waves_n));
+  hipLaunchKernelGGL(gemm_rk_kernel<EPI>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t wgrad(const bf16 *Xp8, const bf16 *Zp8, int64_t mp, int K, int N, float *partial, float *out,
+                        hipStream_t s) {
+  const int chunks = (int)((mp + kWgradChunk - 1) / kWgradChunk);
+  GemmWG g{Xp8, Zp8, mp, K, N, partial};
+  const int tiles = (K / 32) * (N / 32);
+  hipLaunchKernelGGL(gemm_wgrad_kernel, dim3(blocks_for(tiles, 4), chunks), dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(blocks_for(K * N, 256)), dim3(256), 0, s, (const float *)partial,
+                     chunks, K * N, out);
+  return hipGetLastError();
+}
+
+static hipError_t colsum(const bf16 *Z, int64_t mp, int N, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(N, 64)), dim3(64), 0, s, Z, mp, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_input(const float *x, int64_t m, const MlpActs &A, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_input_kernel, dim3(blocks_for(A.mp * kMlpIn, 256)), dim3(256), 0, s, x, m, A.mp, A.a0,
+                     A.a0p8);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpWeights &W, const MlpActs &A, hipStream_t s) {
+  GemmRK g{};
+  g.mp = A.mp;
+  g.A = A.a0, g.Bt = W.wt1, g.N = kMlpHidden, g.K = kMlpIn, g.bias = W.master + kOffB1;
+  g.out = A.a1, g.out_p8 = A.a1p8;
+  hipError_t e = gemm_rk<kEpiRelu>(g, s);
+  if (e != hipSuccess) return e;
+  g.A = A.a1, g.Bt = W.wt2, g.N = kMlpHidden, g.K = kMlpHidden, g.bias = W.master + kOffB2;
+  g.out = A.a2, g.out_p8 = A.a2p8;
+  if ((e = gemm_rk<kEpiRelu>(g, s)) != hipSuccess) return e;
+  g.A = A.a2, g.Bt = W.wt3, g.N = kMlpOut, g.K = kMlpHidden, g.bias = W.master + kOffB3;
+  g.out = nullptr, g.out_p8 = nullptr, g.out_f32 = A.y;
+  return gemm_rk<kEpiOut>(g, s);
+}
+
+hipError_t launch_mlp_backward(const MlpWeights &W, const MlpActs &A, const MlpGrads &G, const float *target,
+                               const float *weight, int64_t m, hipStream_t s) {
+  const int64_t mp = A.mp;
+  const int64_t n_el = mp * kMlpOut;
+  const unsigned lb = blocks_for(n_el, 256);
+  hipLaunchKernelGGL(mlp_loss_kernel, dim3(lb), dim3(256), 0, s, (const float *)A.y, target, weight, m, mp,
+                     (float)(2.0 / (double)m), G.g3, G.g3p8, G.loss_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, (const float *)G.loss_part, (int)lb,
+                     (float)(1.0 / (double)m), G.loss);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // layer 3
+  if ((e = wgrad(A.a2p8, G.g3p8, mp, kMlpHidden, kMlpOut, G.partial, G.grads + kOffW3, s)) != hipSuccess) return e;
+  if ((e = colsum(G.g3, mp, kMlpOut, G.grads + kOffB3, s)) != hipSuccess) return e;
+  GemmRK g{};
+  g.mp = mp;
+  g.A = G.g3, g.Bt = W.wr3, g.N = kMlpHidden, g.K = kMlpOut, g.mask = A.a2, g.out = G.g2, g.out_p8 = G.g2p8;
+  if ((e = gemm_rk<kEpiMask>(g, s)) != hipSuccess) return e;
+  // layer 2
+  if ((e = wgrad(A.a1p8, G.g2p8, mp, kMlpHidden, kMlpHidden, G.partial, G.grads + kOffW2, s)) != hipSuccess)
+    return e;
+  if ((e = colsum(G.g2, mp, kMlpHidden, G.grads + kOffB2, s)) != hipSuccess) return e;
+  g.A = G.g2, g.Bt = W.wr2, g.N = kMlpHidden, g.K = kMlpHidden, g.mask = A.a1, g.out = G.g1, g.out_p8 = G.g1p8;
+  if ((e = gemm_rk<kEpiMask>(g, s)) != hipSuccess) return e;
+  // layer 1
+  if ((e = wgrad(A.a0p8, G.g1p8, mp, kMlpIn, kMlpHidden, G.partial, G.grads + kOffW1, s)) != hipSuccess) return e;
+  return colsum(G.g1, mp, kMlpHidden, G.grads + kOffB1, s);
+}
+
+hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grads, const AdamStep &a, bf16 *wt1,
+                           bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, master, m, v, grads, a,
+                     wt1, wt2, wt3, wr2, wr3);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_refresh(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(mlp_refresh_kernel, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, master, wt1, wt2, wt3,
+                     wr2, wr3);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const PopRows &R, int64_t row0, int64_t n, const float *genotypes, float *x, bf16 *a0,
+                         int64_t a0_rows, hipStream_t s) {
+  const int64_t rows = a0 ? a0_rows : n;
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(encode_kernel, dim3(blocks_for(rows, 128)), dim3(128), 0, s, R, row0, n, genotypes, x, a0,
+                     a0_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_moves(const PopRows &R, const float *from, const float *to, float *out, hipStream_t s) {
+  if (R.n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(moves_kernel, dim3(blocks_for(R.n_rows, 128)), dim3(128), 0, s, R, from, to, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const PopRows &R, int64_t row0, int64_t n, const float *genotypes, const float *y,
+                         float alpha_max, uint64_t seed, int32_t generation, float *proposals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, R, row0, n, genotypes, y, alpha_max,
+                     seed, generation, proposals);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const PopRows &R, const float *prop, const float *prop_e, float *pop, float *pop_e,
+                         const int32_t *gen_reached, int32_t skip_reached, hipStream_t s) {
+  if (R.n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(select_kernel, dim3(blocks_for(R.n_rows, 128)), dim3(128), 0, s, R, prop, prop_e, pop, pop_e,
+                     gen_reached, skip_reached);
+  return hipGetLastError();
+}
+
+}  // namespace dock

@@ -10,7 +10,7 @@
 
 namespace dock {
 
-enum : uint64_t { kPurposeInit = 1, kPurposeSelect = 2, kPurposeCross = 3 };
+enum : uint64_t { kPurposeInit = 1, kPurposeSelect = 2, kPurposeCross = 3, kPurposeProposal = 4 };
 
 __device__ __forceinline__ void philox4x64_10(uint64_t &x0, uint64_t &x1, uint64_t &x2, uint64_t &x3,
                                               uint64_t k0, uint64_t k1) {

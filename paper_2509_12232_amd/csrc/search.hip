@@ -151,7 +151,10 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
     if (reached < 0 && hit) reached = S.p.first_gen;
   }
   __syncthreads();
-  for (int g = S.p.first_gen; g < S.p.first_gen + S.p.n_gen; ++g) {
+  // with S.stop, the search of a ligand ends once its best has reached the target
+  const bool stop = track && S.stop;
+  const int g_end = (stop && reached >= 0) ? S.p.first_gen : S.p.first_gen + S.p.n_gen;
+  for (int g = S.p.first_gen; g < g_end; ++g) {
     // every trial of the generation is drawn from the population as it stood
     for (int c = 0; c < P; c += NT) {
       const int i = c + t;
@@ -177,6 +180,7 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
     if (track) {
       hit = __syncthreads_or(hit);
       if (reached < 0 && hit) reached = g + 1;
+      if (stop && reached >= 0) break;
     } else {
       __syncthreads();
     }

@@ -58,7 +58,9 @@ class _Params(C.Structure):
     _fields_ = [("pop_size", C.c_int32), ("n_generations", C.c_int32), ("seed", C.c_uint64),
                 ("F", C.c_float), ("CR", C.c_float),
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
-                ("init", C.c_int32), ("first_generation", C.c_int32)]
+                ("init", C.c_int32), ("first_generation", C.c_int32), ("stop_at_target", C.c_int32),
+                ("proposal", C.c_void_p), ("proposal_step", C.c_float), ("proposal_every", C.c_int32),
+                ("proposal_until", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -79,7 +81,20 @@ _SIGS = {
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
     "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
+    "dock_mlp_create": [C.c_int32, C.c_uint64, _P],
+    "dock_mlp_destroy": [_P],
+    "dock_mlp_set_params": [_P, _P],
+    "dock_mlp_get_params": [_P, _P],
+    "dock_mlp_forward": [_P, _P, C.c_int64, _P, _P],
+    "dock_mlp_gradients": [_P, _P, _P, _P, C.c_int32, _P, _P, _P],
+    "dock_mlp_train": [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, _P, _P],
+    "dock_ligand_descriptors": [_P, _P, _P],
+    "dock_mlp_features": [_P, _P, C.c_int32, _P, _P, _P],
+    "dock_mlp_moves": [_P, _P, C.c_int32, _P, _P, _P, _P],
+    "dock_propose": [_P, _P, _P, C.c_int32, C.c_float, C.c_int32, _P, _P, _P],
 }
+DOCK_MLP_IN, DOCK_MLP_HIDDEN, DOCK_MLP_OUT, DOCK_MLP_PARAMS, DOCK_DESC = 96, 256, 32, 98848, 64
+DOCK_MLP_MAX_BATCH = 65536
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -246,11 +261,18 @@ class SearchParams:
     CR: float = 0.9
     init: int = 1
     first_generation: int = 0
+    stop_at_target: int = 0
+    proposal: "Mlp | None" = None
+    proposal_step: float = 1.0
+    proposal_every: int = 0
+    proposal_until: int = 1 << 30
 
     def _c(self) -> _Params:
         return _Params(self.pop_size, self.n_generations, self.seed, self.F, self.CR,
                        (C.c_double * 3)(*self.box_lo), (C.c_double * 3)(*self.box_hi), self.init,
-                       self.first_generation)
+                       self.first_generation, self.stop_at_target,
+                       self.proposal.handle if self.proposal is not None else None, self.proposal_step,
+                       self.proposal_every, self.proposal_until)
 
 
 def dock_de_init(ligs: Ligands, params: SearchParams, population, stream=None):
@@ -289,3 +311,88 @@ def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):
     """Pair terms alone on register coordinates (roofline probe)."""
     _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane, _dptr(out, "float32", "out"),
                                 _stream(stream)))
+
+
+# ---------------------------------------------------------------- learned proposal
+class Mlp:
+    """Owner of a dock_mlp handle (the learned-proposal network)."""
+
+    def __init__(self, handle: C.c_void_p, device: int):
+        self.handle = handle
+        self.device = device
+        self._destroy = _lib.dock_mlp_destroy
+
+    def __del__(self):
+        if getattr(self, "handle", None) and getattr(self, "_destroy", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+
+def dock_mlp_create(device: int = 0, seed: int = 1) -> Mlp:
+    out = C.c_void_p()
+    _check(_lib.dock_mlp_create(device, seed, C.byref(out)))
+    return Mlp(out, device)
+
+
+def dock_mlp_set_params(net: Mlp, params):
+    keep = _Keep()
+    p = np.asarray(params, dtype=np.float32).reshape(-1)
+    if p.size != DOCK_MLP_PARAMS:
+        raise ValueError(f"expected {DOCK_MLP_PARAMS} parameters")
+    _check(_lib.dock_mlp_set_params(net.handle, keep.arr(p, np.float32)))
+
+
+def dock_mlp_get_params(net: Mlp) -> np.ndarray:
+    out = np.empty(DOCK_MLP_PARAMS, np.float32)
+    _check(_lib.dock_mlp_get_params(net.handle, C.c_void_p(out.ctypes.data)))
+    return out
+
+
+def dock_mlp_forward(net: Mlp, x, y, stream=None):
+    """x: float32 [n, 96] device tensor; y: float32 [n, 32] device tensor."""
+    n = int(x.shape[0])
+    if y.numel() < n * DOCK_MLP_OUT:
+        raise ValueError("y too small")
+    _check(_lib.dock_mlp_forward(net.handle, _dptr(x, "float32", "x"), n, _dptr(y, "float32", "y"),
+                                 _stream(stream)))
+
+
+def dock_mlp_gradients(net: Mlp, x, target, grads, loss, weight=None, stream=None):
+    n = int(x.shape[0])
+    _check(_lib.dock_mlp_gradients(net.handle, _dptr(x, "float32", "x"), _dptr(target, "float32", "target"),
+                                   _dptr(weight, "float32", "weight"), n, _dptr(grads, "float32", "grads"),
+                                   _dptr(loss, "float32", "loss"), _stream(stream)))
+
+
+def dock_mlp_train(net: Mlp, x, target, batch: int, n_steps: int, lr: float, weight=None, losses=None,
+                   stream=None):
+    n = int(x.shape[0])
+    _check(_lib.dock_mlp_train(net.handle, _dptr(x, "float32", "x"), _dptr(target, "float32", "target"),
+                               _dptr(weight, "float32", "weight"), n, batch, n_steps, lr,
+                               _dptr(losses, "float32", "losses"), _stream(stream)))
+
+
+def dock_ligand_descriptors(ligs: Ligands, out, stream=None):
+    _check(_lib.dock_ligand_descriptors(ligs.handle, _dptr(out, "float32", "out"), _stream(stream)))
+
+
+def dock_mlp_features(ligs: Ligands, params: SearchParams, population, x, stream=None):
+    P = params._c()
+    _check(_lib.dock_mlp_features(ligs.handle, C.byref(P), int(population.shape[-1]),
+                                  _dptr(population, "float32", "population"), _dptr(x, "float32", "x"),
+                                  _stream(stream)))
+
+
+def dock_mlp_moves(ligs: Ligands, params: SearchParams, from_pop, to_pop, out, stream=None):
+    P = params._c()
+    _check(_lib.dock_mlp_moves(ligs.handle, C.byref(P), int(from_pop.shape[-1]),
+                               _dptr(from_pop, "float32", "from"), _dptr(to_pop, "float32", "to"),
+                               _dptr(out, "float32", "out"), _stream(stream)))
+
+
+def dock_propose(ligs: Ligands, net: Mlp, params: SearchParams, generation: int, alpha_max: float, population,
+                 proposals, stream=None):
+    P = params._c()
+    _check(_lib.dock_propose(ligs.handle, net.handle, C.byref(P), generation, alpha_max,
+                             int(population.shape[-1]), _dptr(population, "float32", "population"),
+                             _dptr(proposals, "float32", "proposals"), _stream(stream)))

@@ -37,7 +37,7 @@ def test_binding_names_match_abi():
     from paper_2509_12232_amd import dock
     for n in declared_entry_points():
         if n in ("dock_last_error", "dock_destroy_pocket", "dock_destroy_ligands", "dock_ligand_pair_count",
-                 "dock_pocket_layout"):
+                 "dock_pocket_layout", "dock_mlp_destroy"):
             continue
         assert hasattr(dock, n), n
 
@@ -52,3 +52,21 @@ def test_host_only_calls():
     assert b"null" in lib.dock_last_error()
     assert lib.dock_destroy_pocket(None) == dock.DOCK_OK
     assert lib.dock_destroy_ligands(None) == dock.DOCK_OK
+
+
+def test_search_params_layout_matches_binding(tmp_path):
+    """The ctypes mirror of dock_search_params has the C struct's field offsets."""
+    import subprocess
+    from paper_2509_12232_amd import dock
+    fields = [f for f, _ in dock._Params._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("{f} %zu\\n", offsetof(dock_search_params, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "dock.h"\nint main(void) {\n' + body +
+                   '  printf("sizeof %zu\\n", sizeof(dock_search_params));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for f in fields:
+        assert int(out[f]) == getattr(dock._Params, f).offset, f
+    assert int(out["sizeof"]) == ctypes.sizeof(dock._Params)

@@ -1,0 +1,402 @@
+"""Learned proposal on the GPU against the FP64 reference (oracle/mlp.py).
+
+Tolerance of the network.  The GPU rounds the operands of every matrix product
+to bfloat16 (8 significant bits) at exactly the points where the reference does
+and accumulates in float32.  The two therefore differ by float32 accumulation
+error (a few units of 2^-24 of the accumulated magnitude) plus, rarely, an
+operand whose bfloat16 rounding falls the other way because of that error,
+which moves that operand by one bfloat16 unit (2^-8 relative).  An output of a
+product sum_k a_k b_k is accepted within TOL * sum_k |a_k||b_k| with TOL = 2^-6
+(four bfloat16 units of the accumulated magnitude, enough for such flips in
+this product and the one before it), and the median error must stay below
+2^-12 of that magnitude -- a wrong index, a transposed operand or a dropped term
+gives errors of order one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import mlp
+from tests._systems import assert_energies_match, system
+
+pytestmark = pytest.mark.gpu
+TOL = 2.0 ** -6
+MEDIAN_TOL = 2.0 ** -12
+
+
+@pytest.fixture(scope="module")
+def dk():
+    from paper_2509_12232_amd import dock
+    return dock
+
+
+def rand_params(seed, w_scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shape in mlp.SHAPES:
+        if name.startswith("W"):
+            p[name] = rng.uniform(-1, 1, shape) * np.sqrt(6.0 / shape[0]) * w_scale
+        else:
+            p[name] = rng.uniform(-0.1, 0.1, shape)
+    flat = mlp.pack(p).astype(np.float32)
+    return flat, mlp.unpack(flat.astype(np.float64))
+
+
+def rand_x(seed, n):
+    return np.random.default_rng(seed).uniform(-1, 1, (n, mlp.N_IN)).astype(np.float32)
+
+
+def check_scaled(gpu, ref, scale, what):
+    err = np.abs(np.asarray(gpu, np.float64) - ref)
+    bad = err > TOL * scale + 1e-7
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} outside; worst {err[bad].max()} at scale {scale[bad][0]}"
+    assert np.median(err / (scale + 1e-30)) < MEDIAN_TOL, f"{what}: median relative error too large"
+
+
+def net_with(dk, flat):
+    net = dk.dock_mlp_create(0, 1)
+    dk.dock_mlp_set_params(net, flat)
+    return net
+
+
+@pytest.mark.parametrize("n", [1, 45, 1000])
+def test_forward_matches_oracle(dk, n):
+    flat, P = rand_params(n)
+    net = net_with(dk, flat)
+    x = rand_x(100 + n, n)
+    y = torch.empty((n, 32), dtype=torch.float32, device="cuda")
+    dk.dock_mlp_forward(net, torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    ref, c = mlp.forward(P, x.astype(np.float64), quantize=True)
+    scale = np.abs(c["a2"]) @ np.abs(c["W"]["W3"]) + np.abs(P["b3"])
+    check_scaled(y.cpu().numpy(), ref, scale, "forward")
+
+
+def test_forward_in_chunks(dk):
+    """More rows than one inference pass holds: rows on both sides of the chunk boundary."""
+    n = 70_001
+    flat, P = rand_params(5)
+    net = net_with(dk, flat)
+    x = rand_x(6, n)
+    y = torch.empty((n, 32), dtype=torch.float32, device="cuda")
+    dk.dock_mlp_forward(net, torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.arange(0, 40), np.arange(65_500, 65_600), np.arange(n - 40, n),
+                                     np.random.default_rng(1).integers(0, n, 1500)]))
+    ref, c = mlp.forward(P, x[rows].astype(np.float64), quantize=True)
+    scale = np.abs(c["a2"]) @ np.abs(c["W"]["W3"]) + np.abs(P["b3"])
+    check_scaled(y.cpu().numpy()[rows], ref, scale, "chunked forward")
+
+
+def test_forward_empty_and_invalid(dk):
+    flat, _ = rand_params(1)
+    net = net_with(dk, flat)
+    x = torch.empty((0, 96), dtype=torch.float32, device="cuda")
+    y = torch.empty((0, 32), dtype=torch.float32, device="cuda")
+    dk.dock_mlp_forward(net, x, y)
+    bad = flat.copy()
+    bad[7] = np.nan
+    with pytest.raises(dk.DockError):
+        dk.dock_mlp_set_params(net, bad)
+    np.testing.assert_array_equal(dk.dock_mlp_get_params(net), flat)
+
+
+@pytest.mark.parametrize("n", [777, 32])
+def test_gradients_match_oracle(dk, n):
+    flat, P = rand_params(20 + n)
+    net = net_with(dk, flat)
+    x = rand_x(30 + n, n)
+    rng = np.random.default_rng(n)
+    t = rng.uniform(-1, 1, (n, 32)).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    grads = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    dk.dock_mlp_gradients(net, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), grads, loss,
+                          weight=torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    y, c = mlp.forward(P, x.astype(np.float64), True)
+    T, W = t.astype(np.float64), w.astype(np.float64)
+    g = mlp.backward(P, c, y, T, W)
+    L = mlp.loss(y, T, W)
+    assert abs(float(loss.cpu()[0]) - L) <= 1e-3 * abs(L)
+    G = mlp.unpack(grads.cpu().numpy().astype(np.float64))
+    # back-propagated errors of each layer as the reference rounds them
+    q = mlp.bf16
+    g3 = q((2.0 / n) * W[:, None] * (y - T))
+    g2 = q((g3 @ c["W"]["W3"].T) * (c["a2"] > 0))
+    g1 = q((g2 @ c["W"]["W2"].T) * (c["a1"] > 0))
+    for name, a, e in (("W3", c["a2"], g3), ("W2", c["a1"], g2), ("W1", c["a0"], g1)):
+        check_scaled(G[name], g[name], np.abs(a).T @ np.abs(e), name)
+    for name, e in (("b3", g3), ("b2", g2), ("b1", g1)):
+        check_scaled(G[name], g[name], np.abs(e).sum(axis=0), name)
+
+
+def test_adam_step_matches_oracle(dk):
+    n, lr = 256, 1e-3
+    flat, P = rand_params(41)
+    net = net_with(dk, flat)
+    x = rand_x(42, n)
+    t = np.random.default_rng(43).uniform(-1, 1, (n, 32)).astype(np.float32)
+    dk.dock_mlp_train(net, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), batch=n, n_steps=1, lr=lr)
+    after = dk.dock_mlp_get_params(net).astype(np.float64)
+    y, c = mlp.forward(P, x.astype(np.float64), True)
+    g = mlp.backward(P, c, y, t.astype(np.float64))
+    P1 = {k: v.copy() for k, v in P.items()}
+    m = {k: np.zeros_like(v) for k, v in P.items()}
+    v = {k: np.zeros_like(x_) for k, x_ in P.items()}
+    mlp.adam(P1, g, m, v, 1, lr)
+    ref = mlp.pack(P1)
+    gflat = np.abs(mlp.pack(g))
+    # the first step is -lr g / (|g| + eps): where |g| exceeds twice the gradient
+    # tolerance its sign (hence the step) is the same on both sides
+    q = mlp.bf16
+    g3 = q((2.0 / n) * (y - t.astype(np.float64)))
+    g2 = q((g3 @ c["W"]["W3"].T) * (c["a2"] > 0))
+    g1 = q((g2 @ c["W"]["W2"].T) * (c["a1"] > 0))
+    scale = mlp.pack({"W1": np.abs(c["a0"]).T @ np.abs(g1), "b1": np.abs(g1).sum(0),
+                      "W2": np.abs(c["a1"]).T @ np.abs(g2), "b2": np.abs(g2).sum(0),
+                      "W3": np.abs(c["a2"]).T @ np.abs(g3), "b3": np.abs(g3).sum(0)})
+    sure = (gflat > 2 * TOL * scale + 1e-7) & (gflat > 1e-4)
+    assert sure.mean() > 0.3, sure.mean()
+    np.testing.assert_allclose(after[sure], ref[sure], rtol=0, atol=1e-6 * lr + 2e-7 * np.abs(ref[sure]).max())
+    assert np.all(np.abs(after - flat) <= lr * (1 + 1e-5) + 1e-7)
+
+
+def test_training_reduces_loss(dk):
+    rng = np.random.default_rng(9)
+    n = 4096
+    x = rng.uniform(-1, 1, (n, 96)).astype(np.float32)
+    A = rng.standard_normal((96, 32)) / np.sqrt(96)
+    t = np.tanh(x.astype(np.float64) @ A).astype(np.float32)
+    net = dk.dock_mlp_create(0, 3)
+    losses = torch.empty(200, dtype=torch.float32, device="cuda")
+    dk.dock_mlp_train(net, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), batch=512, n_steps=200, lr=2e-3,
+                      losses=losses)
+    L = losses.cpu().numpy()
+    assert np.all(np.isfinite(L))
+    assert L[-8:].mean() < 0.3 * L[:8].mean(), (L[:8], L[-8:])
+
+
+def test_train_rejects_bad_shapes(dk):
+    net = dk.dock_mlp_create(0, 1)
+    x = torch.zeros((100, 96), dtype=torch.float32, device="cuda")
+    t = torch.zeros((100, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(dk.DockError):
+        dk.dock_mlp_train(net, x, t, batch=30, n_steps=1, lr=1e-3)   # 100 not a multiple of 30
+    with pytest.raises(dk.DockError):
+        dk.dock_mlp_train(net, x, t, batch=100, n_steps=1, lr=float("nan"))
+
+
+# ----------------------------------------------------------------- genotype side
+def ligand_set():
+    """Ligands of several sizes, one with more torsions than the encoding keeps."""
+    specs = [(12, 2), (30, 7), (45, 12), (60, 28), (8, 0)]
+    return [synth.make_ligand(1, 300 + i, n, k, 8) for i, (n, k) in enumerate(specs)]
+
+
+def population(ligs, pop, lo, hi, seed):
+    stride = 7 + max(lg.n_torsions for lg in ligs)
+    rows = []
+    for i, lg in enumerate(ligs):
+        rows.append(synth.sample_genotypes(seed + i, pop, lg.n_torsions, stride, lo, hi))
+    P = np.stack(rows).astype(np.float32)
+    # special rows: zero and negative-w quaternions, translations on the box faces, +-pi torsions
+    P[0, 0, 3:7] = 0
+    P[1, 1, 3] = -abs(P[1, 1, 3]) - 0.1
+    P[2, 2, :3] = lo
+    P[2, 3, :3] = hi
+    P[3, 4, 7:9] = [np.float32(np.pi), np.float32(-np.pi)]
+    return P
+
+
+@pytest.fixture(scope="module")
+def learn_sys(dk):
+    ff, rec, grid, maps = system(0)
+    ligs = ligand_set()
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    L = dk.dock_create_ligands(pocket, ligs)
+    lo, hi = synth.pocket_box(grid)
+    return dict(ff=ff, grid=grid, maps=maps, ligs=ligs, pocket=pocket, L=L, lo=np.asarray(lo), hi=np.asarray(hi))
+
+
+def test_descriptors_match_oracle(dk, learn_sys):
+    S = learn_sys
+    out = torch.empty((len(S["ligs"]), 64), dtype=torch.float32, device="cuda")
+    dk.dock_ligand_descriptors(S["L"], out)
+    got = out.cpu().numpy()
+    for i, lg in enumerate(S["ligs"]):
+        n_pairs = len(oracle.ligand_info(lg, 8)[0])
+        np.testing.assert_allclose(got[i], mlp.descriptor(lg, n_pairs), rtol=0, atol=1e-6)
+
+
+def test_features_and_moves_match_oracle(dk, learn_sys):
+    S = learn_sys
+    pop = 37
+    A = population(S["ligs"], pop, S["lo"], S["hi"], 70)
+    B = population(S["ligs"], pop, S["lo"], S["hi"], 90)
+    p = dk.SearchParams(pop_size=pop, n_generations=0, seed=1, box_lo=tuple(S["lo"]), box_hi=tuple(S["hi"]))
+    x = torch.empty((len(S["ligs"]) * pop, 96), dtype=torch.float32, device="cuda")
+    mv = torch.empty((len(S["ligs"]) * pop, 32), dtype=torch.float32, device="cuda")
+    dk.dock_mlp_features(S["L"], p, torch.from_numpy(A).cuda(), x)
+    dk.dock_mlp_moves(S["L"], p, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), mv)
+    x, mv = x.cpu().numpy(), mv.cpu().numpy()
+    for li, lg in enumerate(S["ligs"]):
+        d = mlp.descriptor(lg, len(oracle.ligand_info(lg, 8)[0]))
+        for i in range(pop):
+            r = li * pop + i
+            f = mlp.encode(A[li, i].astype(np.float64), lg.n_torsions, S["lo"], S["hi"])
+            np.testing.assert_allclose(x[r, :32], f, rtol=0, atol=2e-6, err_msg=f"features row {r}")
+            np.testing.assert_allclose(x[r, 32:], d, rtol=0, atol=1e-6)
+            m = mlp.move(A[li, i].astype(np.float64), B[li, i].astype(np.float64), lg.n_torsions, S["lo"], S["hi"])
+            np.testing.assert_allclose(mv[r, :7], m[:7], rtol=0, atol=2e-6, err_msg=f"move row {r}")
+            dt = (mv[r, 7:] - m[7:] + 1.0) % 2.0 - 1.0   # torsion moves compared modulo a full turn
+            np.testing.assert_allclose(dt, 0.0, atol=2e-6, err_msg=f"move row {r}")
+
+
+def oracle_alpha(seed, ind, gen, lig, alpha_max):
+    """alpha = alpha_max (1 - u), u the first uniform of the (ind, gen, lig, purpose 4) stream."""
+    w = oracle.philox4x64((ind, gen, lig, 4 << 32), (seed, 0))
+    u = (int(w[0]) & 0xFFFFFFFF) >> 8
+    return alpha_max * (1.0 - u / 16777216.0)
+
+
+def oracle_proposals(S, P, A, pop, seed, gen, alpha_max):
+    out = np.empty(A.shape, np.float64)
+    y_all, scale_all = [], []
+    for li, lg in enumerate(S["ligs"]):
+        d = mlp.descriptor(lg, len(oracle.ligand_info(lg, 8)[0]))
+        X = np.stack([np.concatenate([mlp.encode(A[li, i].astype(np.float64), lg.n_torsions, S["lo"], S["hi"]), d])
+                      for i in range(pop)])
+        y, c = mlp.forward(P, X, True)
+        scale = np.abs(c["a2"]) @ np.abs(c["W"]["W3"]) + np.abs(P["b3"])
+        for i in range(pop):
+            a = oracle_alpha(seed, i, gen, li, alpha_max)
+            out[li, i] = mlp.decode(A[li, i].astype(np.float64), y[i], lg.n_torsions, S["lo"], S["hi"], a)
+        y_all.append(y)
+        scale_all.append(scale)
+    return out, np.stack(y_all), np.stack(scale_all)
+
+
+def proposal_tolerance(S, scale, alpha_max, stride):
+    """Per-gene bound on |GPU - reference| proposal: alpha * (gene scale) * 2 TOL * output scale."""
+    t = 2 * TOL * scale * alpha_max + 1e-5
+    tol = np.zeros(scale.shape[:2] + (stride,))
+    h = (S["hi"] - S["lo"]) / 2
+    tol[..., :3] = t[..., :3] * h
+    tol[..., 3:7] = t[..., 3:7]
+    k = min(stride - 7, 25)
+    tol[..., 7:7 + k] = t[..., 7:7 + k] * np.pi
+    tol[..., 7 + k:] = 0
+    return tol + 2e-6
+
+
+def test_proposals_match_oracle(dk, learn_sys):
+    S = learn_sys
+    pop, seed, gen, amax = 29, 11, 3, 0.7
+    flat, P = rand_params(77, w_scale=0.7)
+    net = net_with(dk, flat)
+    A = population(S["ligs"], pop, S["lo"], S["hi"], 500)
+    p = dk.SearchParams(pop_size=pop, n_generations=0, seed=seed, box_lo=tuple(S["lo"]), box_hi=tuple(S["hi"]))
+    out = torch.empty(A.shape, dtype=torch.float32, device="cuda")
+    dk.dock_propose(S["L"], net, p, gen, amax, torch.from_numpy(A).cuda(), out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref, _, scale = oracle_proposals(S, P, A, pop, seed, gen, amax)
+    tol = proposal_tolerance(S, scale, amax, A.shape[2])
+    diff = np.abs(got - ref)
+    tors = diff[..., 7:]
+    diff[..., 7:] = np.minimum(tors, np.abs(tors - 2 * np.pi))    # torsions modulo a full turn
+    assert np.all(diff <= tol), np.argwhere(diff > tol)[:5]
+    # genes past the encoded torsions are copied unchanged
+    np.testing.assert_array_equal(got[3, :, 7 + 25:7 + 28], A[3, :, 7 + 25:7 + 28])
+
+
+def test_learned_init_round(dk, learn_sys):
+    """init = 1, no generations: each individual is the better (by exact score) of
+    its random initial genotype and its proposal."""
+    S = learn_sys
+    pop, seed, amax = 24, 5, 0.6
+    flat, P = rand_params(88, w_scale=0.7)
+    net = net_with(dk, flat)
+    nl = len(S["ligs"])
+    stride = 7 + max(lg.n_torsions for lg in S["ligs"])
+    p = dk.SearchParams(pop_size=pop, n_generations=0, seed=seed, box_lo=tuple(S["lo"]), box_hi=tuple(S["hi"]),
+                        proposal=net, proposal_step=amax)
+    popu = torch.zeros((nl, pop, stride), dtype=torch.float32, device="cuda")
+    pe = torch.zeros((nl, pop), dtype=torch.float32, device="cuda")
+    bg = torch.zeros((nl, stride), dtype=torch.float32, device="cuda")
+    be = torch.zeros(nl, dtype=torch.float32, device="cuda")
+    dk.dock_search(S["pocket"], S["L"], p, popu, pe, bg, be)
+    got, ge = popu.cpu().numpy(), pe.cpu().numpy()
+    op = oracle.SearchParams(pop_size=pop, n_generations=0, seed=seed, box_lo=tuple(S["lo"]), box_hi=tuple(S["hi"]))
+    init = np.stack([oracle.de_init(lg, op, li, stride) for li, lg in enumerate(S["ligs"])])
+    prop, _, scale = oracle_proposals(S, P, init, pop, seed, 0, amax)
+    tol = proposal_tolerance(S, scale, amax, stride)
+    kept = replaced = 0
+    for li, lg in enumerate(S["ligs"]):
+        e_init = oracle.score_poses(S["grid"], S["maps"], S["ff"], [lg], init[li])
+        e_prop = oracle.score_poses(S["grid"], S["maps"], S["ff"], [lg], prop[li].astype(np.float32))
+        # the energies handed back are the scores of the genotypes handed back
+        e_got = oracle.score_poses(S["grid"], S["maps"], S["ff"], [lg], got[li])
+        assert_energies_match(ge[li], e_got, what=f"ligand {li} energies")
+        for i in range(pop):
+            is_init = np.array_equal(got[li, i], init[li, i])
+            d = np.abs(got[li, i] - prop[li, i])
+            d[7:] = np.minimum(d[7:], np.abs(d[7:] - 2 * np.pi))
+            is_prop = np.all(d <= tol[li, i])
+            assert is_init or is_prop, (li, i)
+            margin = 0.5 + 0.05 * max(abs(e_init[i]), abs(e_prop[i]))
+            if e_prop[i] < e_init[i] - margin:
+                assert is_prop, (li, i, e_init[i], e_prop[i])
+                replaced += 1
+            elif e_prop[i] > e_init[i] + margin:
+                assert is_init, (li, i, e_init[i], e_prop[i])
+                kept += 1
+        assert be.cpu().numpy()[li] == ge[li].min()
+    assert kept > 0 and replaced > 0, (kept, replaced)
+
+
+def test_learned_search_rounds_and_stop(dk, learn_sys):
+    S = learn_sys
+    pop, gens = 32, 30
+    net = dk.dock_mlp_create(0, 9)
+    nl = len(S["ligs"])
+    stride = 7 + max(lg.n_torsions for lg in S["ligs"])
+
+    def run(target_value, stop, every=10):
+        p = dk.SearchParams(pop_size=pop, n_generations=gens, seed=2, box_lo=tuple(S["lo"]),
+                            box_hi=tuple(S["hi"]), proposal=net, proposal_step=0.5, proposal_every=every,
+                            proposal_until=25, stop_at_target=stop)
+        popu = torch.zeros((nl, pop, stride), dtype=torch.float32, device="cuda")
+        pe = torch.zeros((nl, pop), dtype=torch.float32, device="cuda")
+        bg = torch.zeros((nl, stride), dtype=torch.float32, device="cuda")
+        be = torch.zeros(nl, dtype=torch.float32, device="cuda")
+        tg = torch.full((nl,), target_value, dtype=torch.float32, device="cuda")
+        gr = torch.zeros(nl, dtype=torch.int32, device="cuda")
+        dk.dock_search(S["pocket"], S["L"], p, popu, pe, bg, be, target=tg, gen_reached=gr)
+        torch.cuda.synchronize()
+        return popu.cpu().numpy(), pe.cpu().numpy(), be.cpu().numpy(), gr.cpu().numpy()
+
+    a = run(-1e30, 0)
+    b = run(-1e30, 0)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)        # deterministic
+    assert np.all(a[3] == -1)
+    for li, lg in enumerate(S["ligs"]):
+        e = oracle.score_poses(S["grid"], S["maps"], S["ff"], [lg], a[0][li])
+        assert_energies_match(a[1][li], e, what=f"ligand {li} energies")
+    # a target every population meets at once: reached after 0 generations, and
+    # with stop_at_target nothing further runs
+    c = run(1e30, 1)
+    assert np.all(c[3] == 0)
+    d = run(1e30, 1, every=0)
+    np.testing.assert_array_equal(c[0], d[0])
+    # a target reached part-way: every ligand that reports a generation has a best <= target
+    tgt = float(np.median(a[2])) + 2.0
+    f = run(tgt, 1)
+    for li in range(nl):
+        if f[3][li] >= 0:
+            assert f[2][li] <= tgt + 1e-6
+        else:
+            assert f[2][li] > tgt

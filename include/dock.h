@@ -188,9 +188,10 @@ typedef struct {
   /* Learned proposal (not part of the paper's search; NULL = plain DE).  A
    * proposal round replaces each individual by dock_propose's proposal when the
    * proposal scores <= the individual (the search's own greedy rule).  Rounds run
-   * right after the initial population (init = 1) and then before generation g
-   * for every g = first_generation + k * proposal_every (k >= 1, proposal_every
-   * > 0) with g < proposal_until. */
+   * right after the initial population (init = 1) and before every generation g
+   * of the call that is a positive multiple of proposal_every (> 0) with g <
+   * proposal_until -- absolute generation indices, so a search split into
+   * resumed calls runs the same rounds as one call. */
   const dock_mlp *proposal;
   float proposal_step;      /* alpha_max of dock_propose, > 0 */
   int32_t proposal_every;   /* >= 0 (0: only the round after the initial population) */
@@ -271,12 +272,17 @@ dock_status dock_mlp_forward(const dock_mlp *net, const float *x, int64_t n, flo
 dock_status dock_mlp_gradients(dock_mlp *net, const float *x, const float *target, const float *weight, int32_t n,
                                float *grads, float *loss, void *stream);
 /* n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
- * minibatches of `batch` consecutive rows: step s uses rows starting at
- * (s * batch) mod n_rows.  n_rows must be a multiple of batch, 1 <= batch <=
- * DOCK_MLP_MAX_BATCH.  losses (device float[n_steps], may be NULL) receives each
- * step's loss before its update.  Calls on one network must not overlap. */
-dock_status dock_mlp_train(dock_mlp *net, const float *x, const float *target, const float *weight, int64_t n_rows,
-                           int32_t batch, int32_t n_steps, float lr, float *losses, void *stream);
+ * minibatches of `batch` rows of the data set x [n_data][96], target
+ * [n_data][32], weight [n_data] (NULL = 1).  The rows trained on are
+ * order[0 .. n_rows) (device int32, each in [0, n_data), checked on the host
+ * with a synchronous copy), or 0 .. n_rows-1 when order is NULL (then n_rows <=
+ * n_data); step s takes positions (s * batch) mod n_rows onwards.  n_rows must
+ * be a multiple of batch, 1 <= batch <= DOCK_MLP_MAX_BATCH.  losses (device
+ * float[n_steps], may be NULL) receives each step's loss before its update.
+ * Calls on one network must not overlap. */
+dock_status dock_mlp_train(dock_mlp *net, const float *x, const float *target, const float *weight, int64_t n_data,
+                           const int32_t *order, int64_t n_rows, int32_t batch, int32_t n_steps, float lr,
+                           float *losses, void *stream);
 
 /* Descriptor of every ligand, out [n_ligands][64] (device float32): [0, 32) the
  * fraction of its atoms of each type; 32 torsions / 20; 33 atoms / 96; 34 mean

@@ -690,30 +690,6 @@ static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, Searc
   return e;
 }
 
-// Scores of a whole population [n_ligs][pop][g_stride] into energies [n_ligs][pop].
-static hipError_t score_population(const dock_pocket *p, const dock_ligands *L, int32_t pop, int32_t g_stride,
-                                   const float *genotypes, float *energies, hipStream_t s) {
-  ScoreLaunch a = make_score(p, L);
-  a.poses_per_ligand = pop;
-  a.genotypes = genotypes;
-  a.g_stride = g_stride;
-  a.n_poses = (int64_t)L->n_ligs * pop;
-  a.energies = energies;
-  return launch_score(a, s);
-}
-
-// A learned-proposal round before generation gen: proposals of the population,
-// their exact scores, greedy replacement.
-static hipError_t proposal_round(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
-                                 const PopRows &R, int32_t gen, float *pop, float *pop_e, float *prop, float *prop_e,
-                                 const int32_t *gen_reached, int32_t stop, hipStream_t s, const char **step) {
-  *step = "proposals";
-  hipError_t e = run_proposals(q->proposal, R, q->proposal_step, q->seed, gen, pop, prop, s);
-  if (e == hipSuccess) *step = "proposal scores", e = score_population(p, L, R.pop, R.g_stride, prop, prop_e, s);
-  if (e == hipSuccess) *step = "proposal selection", e = launch_select(R, prop, prop_e, pop, pop_e, gen_reached, stop, s);
-  return e;
-}
-
 extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
                                    int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                                    float *best_energies, const float *target, int32_t *gen_reached, void *stream) {
@@ -754,44 +730,57 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   S.gen_reached = track ? gen_reached : nullptr;
   S.stop = q->stop_at_target ? 1 : 0;
   int32_t *queues = nullptr;
-  float *prop_e = nullptr;
   const char *step = "search buffers";
   hipError_t e = hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&queues, sizeof(int32_t) * L->buckets.size(), s);
-  if (e == hipSuccess && net) e = hipMallocAsync((void **)&prop_e, sizeof(float) * n, s);
   if (e == hipSuccess && !net) {
     e = search_pass(p, L, S, queues, s, &step);
   } else if (e == hipSuccess) {
-    // Learned proposals: the trial buffer holds the proposals of a round; the
-    // generations between rounds run as plain persistent passes that resume.
+    // Learned proposals: a round fills the trial buffer with one proposal per
+    // individual; the next persistent pass scores them and takes each greedily
+    // before its generations (the pass's DE trials reuse that buffer afterwards).
     const PopRows R = make_pop_rows(L, P, g_stride, q->box_lo, q->box_hi);
     const int g0 = q->first_generation, g_end = g0 + q->n_generations;
+    const int every = q->proposal_every;
+    auto propose = [&](int gen) {
+      step = "proposals";
+      return run_proposals(net, R, q->proposal_step, q->seed, gen, population, S.trials, s);
+    };
+    bool pending = false;
     if (q->init) {
-      step = "initial population";
-      e = launch_de_init(L->view(), S.p, g_stride, population, s);
-      if (e == hipSuccess) e = score_population(p, L, P, g_stride, population, pop_energy, s);
-      if (e == hipSuccess && track) e = launch_fill_i32(gen_reached, nl, -1, s);
-      if (e == hipSuccess)
-        e = proposal_round(p, L, q, R, g0, population, pop_energy, S.trials, prop_e, S.gen_reached, S.stop, s, &step);
+      // the initial population and its scores, then the first round
+      SearchLaunch T = S;
+      T.p.n_gen = 0;
+      e = search_pass(p, L, T, queues, s, &step);
+      if (e == hipSuccess) e = propose(g0);
+      pending = true;
+    } else if (every > 0 && g0 > 0 && g0 % every == 0 && g0 < q->proposal_until && g0 < g_end) {
+      // later rounds come before the generations g > 0 that are multiples of
+      // proposal_every (g < proposal_until), so a search split into resumed
+      // calls runs the same rounds as one call
+      e = propose(g0);
+      pending = true;
     }
     int g = g0;
-    do {
+    while (e == hipSuccess) {
       int seg_end = g_end;
-      if (q->proposal_every > 0) {
-        const int64_t nb = g0 + ((int64_t)(g - g0) / q->proposal_every + 1) * q->proposal_every;
+      if (every > 0) {
+        const int64_t nb = ((int64_t)g / every + 1) * every;
         if (nb < q->proposal_until && nb < g_end) seg_end = (int)nb;
       }
       SearchLaunch T = S;
       T.init = 0;
       T.p.first_gen = g;
       T.p.n_gen = seg_end - g;
-      if (e == hipSuccess) e = search_pass(p, L, T, queues, s, &step);
+      T.proposals = pending ? S.trials : nullptr;
+      e = search_pass(p, L, T, queues, s, &step);
+      pending = false;
       g = seg_end;
-      if (e == hipSuccess && g < g_end)
-        e = proposal_round(p, L, q, R, g, population, pop_energy, S.trials, prop_e, S.gen_reached, S.stop, s, &step);
-    } while (g < g_end && e == hipSuccess);
+      if (g >= g_end) break;
+      if (e == hipSuccess) e = propose(g);
+      pending = true;
+    }
   }
-  if (prop_e) (void)hipFreeAsync(prop_e, s);
   if (queues) (void)hipFreeAsync(queues, s);
   if (S.trials) (void)hipFreeAsync(S.trials, s);
   if (e != hipSuccess) return hip_err(e, step);

@@ -68,6 +68,7 @@ struct dock_mlp {
   int64_t ws_rows = 0;
   MlpActs A{};
   MlpGrads G{};
+  float *tb = nullptr, *wb = nullptr;  // gathered targets [rows][32] and weights [rows]
   MlpWeights weights() const { return MlpWeights{master, wt1, wt2, wt3, wr2, wr3}; }
   hipError_t ensure_workspace(int64_t mp) {
     if (mp <= ws_rows) return hipSuccess;
@@ -83,11 +84,15 @@ struct dock_mlp {
     MlpGrads g;
     carve_acts(sizer, mp, true, a);
     carve_grads(sizer, mp, g);
+    sizer.take<float>(mp * kMlpOut);
+    sizer.take<float>(mp);
     hipError_t e = hipMalloc((void **)&ws, sizer.off);
     if (e != hipSuccess) return e;
     Carver c{ws};
     carve_acts(c, mp, true, A);
     carve_grads(c, mp, G);
+    tb = c.take<float>(mp * kMlpOut);
+    wb = c.take<float>(mp);
     ws_rows = mp;
     return hipSuccess;
   }
@@ -228,17 +233,18 @@ extern "C" dock_status dock_mlp_forward(const dock_mlp *n, const float *x, int64
   return DOCK_OK;
 }
 
-// Forward + backward of one batch of rows into the network's workspace.
-static hipError_t batch_gradients(dock_mlp *n, const float *x, const float *target, const float *weight, int64_t m,
-                                  hipStream_t s) {
+// Forward + backward of one batch of m rows (source rows order[row0 ..] or
+// row0 ..) into the network's workspace.
+static hipError_t batch_gradients(dock_mlp *n, const float *x, const float *target, const float *weight,
+                                  const int32_t *order, int64_t row0, int64_t m, hipStream_t s) {
   const int64_t mp = pad_rows(m);
   hipError_t e = n->ensure_workspace(mp);
   if (e != hipSuccess) return e;
   MlpActs A = n->A;
   A.mp = mp;
-  e = launch_mlp_input(x, m, A, s);
+  e = launch_mlp_gather(x, target, weight, order, row0, m, A, n->tb, n->wb, s);
   if (e == hipSuccess) e = launch_mlp_forward(n->weights(), A, s);
-  if (e == hipSuccess) e = launch_mlp_backward(n->weights(), A, n->G, target, weight, m, s);
+  if (e == hipSuccess) e = launch_mlp_backward(n->weights(), A, n->G, n->tb, weight ? n->wb : nullptr, m, s);
   return e;
 }
 
@@ -249,27 +255,36 @@ extern "C" dock_status dock_mlp_gradients(dock_mlp *n, const float *x, const flo
   DeviceScope ds(n->device);
   HIP_TRY(ds.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(batch_gradients(n, x, target, weight, rows, s), "network gradients");
+  HIP_TRY(batch_gradients(n, x, target, weight, nullptr, 0, rows, s), "network gradients");
   HIP_TRY(hipMemcpyAsync(grads, n->G.grads, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, s), "copy gradients");
   HIP_TRY(hipMemcpyAsync(loss, n->G.loss, sizeof(float), hipMemcpyDeviceToDevice, s), "copy loss");
   return DOCK_OK;
 }
 
 extern "C" dock_status dock_mlp_train(dock_mlp *n, const float *x, const float *target, const float *weight,
-                                      int64_t n_rows, int32_t batch, int32_t n_steps, float lr, float *losses,
-                                      void *stream) {
+                                      int64_t n_data, const int32_t *order, int64_t n_rows, int32_t batch,
+                                      int32_t n_steps, float lr, float *losses, void *stream) {
   if (!n || !x || !target) return set_err(DOCK_E_INVALID, "null argument");
   if (batch < 1 || batch > DOCK_MLP_MAX_BATCH) return set_err(DOCK_E_INVALID, "batch must be in 1..%d", DOCK_MLP_MAX_BATCH);
   if (n_rows < batch || n_rows % batch != 0) return set_err(DOCK_E_INVALID, "n_rows must be a positive multiple of batch");
+  if (n_data < 1 || n_data > 0x7fffffff) return set_err(DOCK_E_INVALID, "n_data must be in 1..2^31-1");
+  if (!order && n_rows > n_data) return set_err(DOCK_E_INVALID, "n_rows > n_data without an order");
   if (n_steps < 0) return set_err(DOCK_E_INVALID, "n_steps must be >= 0");
   if (!(lr > 0) || !isfinite(lr)) return set_err(DOCK_E_INVALID, "lr must be positive and finite");
   DeviceScope ds(n->device);
   HIP_TRY(ds.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
+  if (order) {
+    // every row index is checked before any kernel reads through it
+    std::vector<int32_t> h(n_rows);
+    HIP_TRY(hipMemcpyAsync(h.data(), order, sizeof(int32_t) * n_rows, hipMemcpyDeviceToHost, s), "copy order");
+    HIP_TRY(hipStreamSynchronize(s), "synchronize");
+    for (int64_t i = 0; i < n_rows; ++i)
+      if (h[i] < 0 || h[i] >= n_data) return set_err(DOCK_E_INVALID, "order[%lld] = %d outside 0..n_data-1", (long long)i, h[i]);
+  }
   for (int32_t st = 0; st < n_steps; ++st) {
     const int64_t off = ((int64_t)st * batch) % n_rows;
-    HIP_TRY(batch_gradients(n, x + off * kMlpIn, target + off * kMlpOut, weight ? weight + off : nullptr, batch, s),
-            "network gradients");
+    HIP_TRY(batch_gradients(n, x, target, weight, order, off, batch, s), "network gradients");
     if (losses) HIP_TRY(hipMemcpyAsync(losses + st, n->G.loss, sizeof(float), hipMemcpyDeviceToDevice, s), "copy loss");
     n->adam_t += 1;
     AdamStep a{lr, 0.9f, 0.999f, 1e-8f, (float)(1.0 - pow(0.9, (double)n->adam_t)),
@@ -336,14 +351,7 @@ extern "C" dock_status dock_mlp_moves(const dock_ligands *L, const dock_search_p
 
 hipError_t run_proposals(const dock_mlp *net, const PopRows &R, float alpha_max, uint64_t seed, int32_t generation,
                          const float *population, float *proposals, hipStream_t s) {
-  return infer_rows(
-      net, R.n_rows, s,
-      [&](int64_t r0, int64_t cnt, const MlpActs &A) {
-        return launch_encode(R, r0, cnt, population, nullptr, A.a0, A.mp, s);
-      },
-      [&](int64_t r0, int64_t cnt, const float *y) {
-        return launch_decode(R, r0, cnt, population, y, alpha_max, seed, generation, proposals, s);
-      });
+  return launch_propose(R, net->weights(), population, alpha_max, seed, generation, proposals, s);
 }
 
 int mlp_device(const dock_mlp *net) { return net->device; }

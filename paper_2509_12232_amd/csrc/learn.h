@@ -57,6 +57,11 @@ struct MlpGrads {
 
 // x: fp32 rows [m][96] -> a0 (and a0p8 if set); rows m..mp-1 zero.
 hipError_t launch_mlp_input(const float *x, int64_t m, const MlpActs &A, hipStream_t s);
+// A training batch of m rows, batch row r taken from source row
+// order[row0 + r] (or row0 + r without order): inputs -> a0 and a0p8, targets ->
+// tb [mp][32], weights -> wb [mp] (when w is set); padding rows zero.
+hipError_t launch_mlp_gather(const float *x, const float *t, const float *w, const int32_t *order, int64_t row0,
+                             int64_t m, const MlpActs &A, float *tb, float *wb, hipStream_t s);
 // a0 -> a1 -> a2 -> y.
 hipError_t launch_mlp_forward(const MlpWeights &W, const MlpActs &A, hipStream_t s);
 // loss and all gradients of the batch (m valid rows) into G.grads / G.loss.
@@ -87,13 +92,11 @@ hipError_t launch_encode(const PopRows &R, int64_t row0, int64_t n, const float 
                          int64_t a0_rows, hipStream_t s);
 // encoded moves from -> to, [n_rows][32]
 hipError_t launch_moves(const PopRows &R, const float *from, const float *to, float *out, hipStream_t s);
-// proposals = decode(genotypes, y, alpha_max * u) for rows [row0, row0 + n), u in (0, 1]
-// from the Philox stream (individual, generation, ligand, proposal purpose)
-hipError_t launch_decode(const PopRows &R, int64_t row0, int64_t n, const float *genotypes, const float *y,
-                         float alpha_max, uint64_t seed, int32_t generation, float *proposals, hipStream_t s);
-// greedy replacement: row takes the proposal when its energy is <= the row's
-// (rows of ligands with gen_reached >= 0 untouched when skip_reached)
-hipError_t launch_select(const PopRows &R, const float *prop, const float *prop_e, float *pop, float *pop_e,
-                         const int32_t *gen_reached, int32_t skip_reached, hipStream_t s);
+// proposals = decode(genotypes, network(encode(genotypes)), alpha_max * u) for
+// every row, u in (0, 1] from the Philox stream (individual, generation, ligand,
+// proposal purpose); one fused launch (encode, the three layers and decode per
+// 32 rows, activations in LDS)
+hipError_t launch_propose(const PopRows &R, const MlpWeights &W, const float *genotypes, float alpha_max,
+                          uint64_t seed, int32_t generation, float *proposals, hipStream_t s);
 
 }  // namespace dock

@@ -141,6 +141,20 @@ __global__ void mlp_input_kernel(const float *x, int64_t m, int64_t mp, bf16 *a0
   if (a0p8) a0p8[p8_index(row, kMlpIn, c)] = h;
 }
 
+__global__ void mlp_gather_kernel(const float *x, const float *t, const float *w, const int32_t *order, int64_t row0,
+                                  int64_t m, int64_t mp, bf16 *a0, bf16 *a0p8, float *tb, float *wb) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mp) return;
+  const int64_t src = r < m ? (order ? (int64_t)order[row0 + r] : row0 + r) : -1;
+  for (int c = 0; c < kMlpIn; ++c) {
+    const bf16 h = (bf16)(src >= 0 ? x[src * kMlpIn + c] : 0.f);
+    a0[r * kMlpIn + c] = h;
+    a0p8[p8_index(r, kMlpIn, c)] = h;
+  }
+  for (int c = 0; c < kMlpOut; ++c) tb[r * kMlpOut + c] = src >= 0 ? t[src * kMlpOut + c] : 0.f;
+  if (wb) wb[r] = src >= 0 ? w[src] : 0.f;
+}
+
 // g = bfloat16((2 / m) w (y - t)) for valid rows, 0 for padding rows; per-block
 // sums of w (y - t)^2 (fixed tree order).
 __global__ __launch_bounds__(256) void mlp_loss_kernel(const float *y, const float *t, const float *w, int64_t m,
@@ -230,15 +244,14 @@ __device__ __forceinline__ float wrapf(float a) {
 }
 
 // unit quaternion with w >= 0; identity for a zero quaternion
+// (selects instead of an early return, so that q stays in registers)
 __device__ __forceinline__ void canonical_q(const float *g, float q[4]) {
   const float nn = g[3] * g[3] + g[4] * g[4] + g[5] * g[5] + g[6] * g[6];
-  if (nn < 1e-24f) {
-    q[0] = 1.f, q[1] = q[2] = q[3] = 0.f;
-    return;
-  }
-  float s = 1.f / sqrtf(nn);
+  const bool ident = nn < 1e-24f;
+  float s = 1.f / sqrtf(ident ? 1.f : nn);
   if (g[3] < 0.f) s = -s;
-  for (int c = 0; c < 4; ++c) q[c] = g[3 + c] * s;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = ident ? (c == 0 ? 1.f : 0.f) : g[3 + c] * s;
 }
 
 __device__ __forceinline__ void box_half(const PopRows &R, int d, float &c, float &h) {
@@ -252,6 +265,7 @@ __device__ void encode_row(const PopRows &R, int64_t r, const float *genotypes, 
   const int lig = (int)(r / R.pop);
   const float *g = genotypes + r * R.g_stride;
   const int nt = min(R.hdr[lig].n_tors, kEncTorsions);
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     float c, h;
     box_half(R, d, c, h);
@@ -292,6 +306,7 @@ __global__ void moves_kernel(PopRows R, const float *from, const float *to, floa
   const float *a = from + r * R.g_stride, *b = to + r * R.g_stride;
   float *o = out + r * kMlpOut;
   const int nt = min(R.hdr[lig].n_tors, kEncTorsions);
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     float c, h;
     box_half(R, d, c, h);
@@ -306,18 +321,16 @@ __global__ void moves_kernel(PopRows R, const float *from, const float *to, floa
   for (int k = 0; k < kEncTorsions; ++k) o[7 + k] = k < nt ? wrapf(b[7 + k] - a[7 + k]) / kPiF : 0.f;
 }
 
-__global__ void decode_kernel(PopRows R, int64_t row0, int64_t n, const float *genotypes, const float *y,
-                              float alpha_max, uint64_t seed, int32_t generation, float *prop) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t r = row0 + i;
+// Proposal of population row r from its network output yy (32 values).
+__device__ void decode_row(const PopRows &R, int64_t r, const float *genotypes, const float *yy, float alpha_max,
+                           uint64_t seed, int32_t generation, float *prop) {
   const int lig = (int)(r / R.pop), ind = (int)(r % R.pop);
   const float *g = genotypes + r * R.g_stride;
-  const float *yy = y + i * kMlpOut;
   float *o = prop + r * R.g_stride;
   DrawStream s(seed, (uint64_t)ind, (uint64_t)generation, (uint64_t)lig, kPurposeProposal);
   const float alpha = alpha_max * (float)(1.0 - s.unit());
   for (int j = 0; j < R.g_stride; ++j) o[j] = g[j];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     float c, h;
     box_half(R, d, c, h);
@@ -331,16 +344,100 @@ __global__ void decode_kernel(PopRows R, int64_t row0, int64_t n, const float *g
   for (int k = 0; k < nt; ++k) o[7 + k] = wrapf(g[7 + k] + alpha * kPiF * yy[7 + k]);
 }
 
-__global__ void select_kernel(PopRows R, const float *prop, const float *prop_e, float *pop, float *pop_e,
-                              const int32_t *gen_reached, int32_t skip_reached) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R.n_rows) return;
-  const int lig = (int)(r / R.pop);
-  if (skip_reached && gen_reached && gen_reached[lig] >= 0) return;
-  const float e = prop_e[r];
-  if (!(e <= pop_e[r])) return;
-  pop_e[r] = e;
-  for (int j = 0; j < R.g_stride; ++j) pop[r * R.g_stride + j] = prop[r * R.g_stride + j];
+// ---------------------------------------------------- fused proposal kernel
+// One wavefront (the whole workgroup) takes 32 population rows through encode,
+// the three layers and decode.  The rows' activations stay in LDS, one padded
+// row per individual (the padding puts consecutive rows' 16-byte fragments in
+// different banks); weight fragments stream from L2, where every wavefront
+// reads the same 196 KB.  The products run in the same k order as the
+// per-layer kernels, so the network output is the same to the bit.
+constexpr int kPropRows = 32;
+constexpr int kHStride = kMlpHidden + 8;  // bfloat16 per LDS row
+
+__device__ __forceinline__ bf16x8 lds_frag(const bf16 *h, int l, int k0) {
+  return *reinterpret_cast<const bf16x8 *>(h + (l & 31) * kHStride + k0 + 8 * (l >> 5));
+}
+
+// acc[t] += h[rows][0..K) * W (Bt = [32 * NT][K]) for NT column tiles of 32
+template <int NT, int K>
+__device__ __forceinline__ void layer_product(const bf16 *h, const bf16 *Bt, int l, f32x16 acc[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+  const bf16 *b = Bt + (l & 31) * K + 8 * (l >> 5);
+  for (int k = 0; k < K; k += 16) {
+    const bf16x8 a = lds_frag(h, l, k);
+    bf16x8 bt[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bt[t] = frag(b + t * 32 * K + k);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bt[t], acc[t]);
+  }
+}
+
+// h[rows][col] = bfloat16(relu(acc + bias[col]))
+template <int NT>
+__device__ __forceinline__ void store_hidden(bf16 *h, const float *bias, int l, const f32x16 acc[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 32 + (l & 31);
+    const float b = bias[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float v = acc[t][r] + b;
+      h[acc_row(r, l) * kHStride + col] = (bf16)(v > 0.f ? v : 0.f);
+    }
+  }
+}
+
+struct ProposeLaunch {
+  PopRows R;
+  MlpWeights W;
+  const float *genotypes;
+  float *proposals;
+  float alpha_max;
+  uint64_t seed;
+  int32_t generation;
+};
+
+__global__ __launch_bounds__(64) void propose_kernel(ProposeLaunch P) {
+  __shared__ __attribute__((aligned(16))) bf16 h[kPropRows * kHStride];
+  const int l = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * kPropRows;
+  const int64_t r = row0 + (l & 31);
+  const bool mine = l < kPropRows;  // lanes 0..31 encode and decode one row each
+  if (mine) {
+    float f[kMlpIn];
+    if (r < P.R.n_rows) {
+      encode_row(P.R, r, P.genotypes, f);
+    } else {
+      for (int j = 0; j < kMlpIn; ++j) f[j] = 0.f;
+    }
+    for (int j = 0; j < kMlpIn; ++j) h[l * kHStride + j] = (bf16)f[j];
+  }
+  __syncthreads();
+  f32x16 acc[kMlpHidden / 32];
+  layer_product<kMlpHidden / 32, kMlpIn>(h, P.W.wt1, l, acc);
+  __syncthreads();
+  store_hidden<kMlpHidden / 32>(h, P.W.master + kOffB1, l, acc);
+  __syncthreads();
+  layer_product<kMlpHidden / 32, kMlpHidden>(h, P.W.wt2, l, acc);
+  __syncthreads();
+  store_hidden<kMlpHidden / 32>(h, P.W.master + kOffB2, l, acc);
+  __syncthreads();
+  f32x16 out[1];
+  layer_product<1, kMlpHidden>(h, P.W.wt3, l, out);
+  __syncthreads();
+  // network outputs as float32 rows of 32 in the same LDS
+  float *y = reinterpret_cast<float *>(h);
+  {
+    const int col = l & 31;
+    const float b = P.W.master[kOffB3 + col];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[acc_row(i, l) * kMlpOut + col] = out[0][i] + b;
+  }
+  __syncthreads();
+  if (mine && r < P.R.n_rows)
+    decode_row(P.R, r, P.genotypes, y + l * kMlpOut, P.alpha_max, P.seed, P.generation, P.proposals);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -378,6 +475,13 @@ static hipError_t colsum(const bf16 *Z, int64_t mp, int N, float *out, hipStream
 hipError_t launch_mlp_input(const float *x, int64_t m, const MlpActs &A, hipStream_t s) {
   hipLaunchKernelGGL(mlp_input_kernel, dim3(blocks_for(A.mp * kMlpIn, 256)), dim3(256), 0, s, x, m, A.mp, A.a0,
                      A.a0p8);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_gather(const float *x, const float *t, const float *w, const int32_t *order, int64_t row0,
+                             int64_t m, const MlpActs &A, float *tb, float *wb, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_gather_kernel, dim3(blocks_for(A.mp, 128)), dim3(128), 0, s, x, t, w, order, row0, m, A.mp,
+                     A.a0, A.a0p8, tb, w ? wb : nullptr);
   return hipGetLastError();
 }
 
@@ -455,19 +559,11 @@ hipError_t launch_moves(const PopRows &R, const float *from, const float *to, fl
   return hipGetLastError();
 }
 
-hipError_t launch_decode(const PopRows &R, int64_t row0, int64_t n, const float *genotypes, const float *y,
-                         float alpha_max, uint64_t seed, int32_t generation, float *proposals, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, R, row0, n, genotypes, y, alpha_max,
-                     seed, generation, proposals);
-  return hipGetLastError();
-}
-
-hipError_t launch_select(const PopRows &R, const float *prop, const float *prop_e, float *pop, float *pop_e,
-                         const int32_t *gen_reached, int32_t skip_reached, hipStream_t s) {
+hipError_t launch_propose(const PopRows &R, const MlpWeights &W, const float *genotypes, float alpha_max,
+                          uint64_t seed, int32_t generation, float *proposals, hipStream_t s) {
   if (R.n_rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(select_kernel, dim3(blocks_for(R.n_rows, 128)), dim3(128), 0, s, R, prop, prop_e, pop, pop_e,
-                     gen_reached, skip_reached);
+  ProposeLaunch P{R, W, genotypes, proposals, alpha_max, seed, generation};
+  hipLaunchKernelGGL(propose_kernel, dim3(blocks_for(R.n_rows, kPropRows)), dim3(64), 0, s, P);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct SearchLaunch {
   int32_t *queue;
   int32_t lds_atoms;     // atom slots per lane in LDS (largest ligand of the launch)
   int32_t stop;          // end a ligand's search once gen_reached is set
+  const float *proposals;  // [n_ligs][pop][g_stride] or null: scored and taken greedily before the generations
 };
 
 constexpr int kSearchMaxThreads = 256;      // wavefronts per search workgroup: up to 4

@@ -139,6 +139,23 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
       }
     }
   }
+  // a round of outside proposals (one per individual): exact score, greedy
+  // replacement -- skipped for a ligand that has already stopped at its target
+  if (S.proposals && !(S.stop && !S.init && S.gen_reached && S.gen_reached[lig] >= 0)) {
+    const float *Q = S.proposals + (int64_t)lig * P * G;
+    for (int c = 0; c < P; c += NT) {
+      const int i = c + t;
+      if (i < P) {
+        const float *pr = Q + (int64_t)i * G;
+        const float e = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, pr, my);
+        if (e <= E[i]) {
+          float *row = pop + (int64_t)i * G;
+          for (int j = 0; j < G; ++j) row[j] = pr[j];
+          E[i] = e;
+        }
+      }
+    }
+  }
   int reached = -1;
   if (track) {
     int hit = 0;

@@ -87,7 +87,7 @@ _SIGS = {
     "dock_mlp_get_params": [_P, _P],
     "dock_mlp_forward": [_P, _P, C.c_int64, _P, _P],
     "dock_mlp_gradients": [_P, _P, _P, _P, C.c_int32, _P, _P, _P],
-    "dock_mlp_train": [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, _P, _P],
+    "dock_mlp_train": [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32, C.c_float, _P, _P],
     "dock_ligand_descriptors": [_P, _P, _P],
     "dock_mlp_features": [_P, _P, C.c_int32, _P, _P, _P],
     "dock_mlp_moves": [_P, _P, C.c_int32, _P, _P, _P, _P],
@@ -364,12 +364,15 @@ def dock_mlp_gradients(net: Mlp, x, target, grads, loss, weight=None, stream=Non
                                    _dptr(loss, "float32", "loss"), _stream(stream)))
 
 
-def dock_mlp_train(net: Mlp, x, target, batch: int, n_steps: int, lr: float, weight=None, losses=None,
+def dock_mlp_train(net: Mlp, x, target, batch: int, n_steps: int, lr: float, weight=None, order=None, losses=None,
                    stream=None):
+    """Adam steps on minibatches of the data set x [n, 96] / target [n, 32]: the rows
+    order[0..] (int32 device tensor of row indices) or all rows in order."""
     n = int(x.shape[0])
+    n_rows = n if order is None else int(order.numel())
     _check(_lib.dock_mlp_train(net.handle, _dptr(x, "float32", "x"), _dptr(target, "float32", "target"),
-                               _dptr(weight, "float32", "weight"), n, batch, n_steps, lr,
-                               _dptr(losses, "float32", "losses"), _stream(stream)))
+                               _dptr(weight, "float32", "weight"), n, _dptr(order, "int32", "order"), n_rows,
+                               batch, n_steps, lr, _dptr(losses, "float32", "losses"), _stream(stream)))
 
 
 def dock_ligand_descriptors(ligs: Ligands, out, stream=None):

@@ -266,6 +266,11 @@ CONFIGS = {
     # 10000 ligands lognormal(ln 32, 0.5) clipped 8..96, torsions 0..20; 12 types, 80^3; 150 x 300
     3: dict(name="uneven persistent batch", n_types=12, grid_n=80, n_ligands=10_000,
             atoms="lognormal", torsions=(0, 20), pop=150, gens=300),
+    # learned proposal vs plain DE on config 3's batch; the network is trained on
+    # plain runs over a disjoint set of 5000 ligands (ids 100000..104999) drawn
+    # from the same size distribution
+    4: dict(name="learned proposal vs plain", n_types=12, grid_n=80, n_ligands=5_000, first_id=100_000,
+            atoms="lognormal", torsions=(0, 20), pop=150, gens=300, tuples=1_000_000),
 }
 
 
@@ -300,7 +305,8 @@ def config_ligands(cfg_id: int, seed: int = 1, count: int | None = None, workers
     c = CONFIGS[cfg_id]
     atoms, tors = config_ligand_sizes(cfg_id, seed)
     m = len(atoms) if count is None else min(count, len(atoms))
-    args = [(seed, i, int(atoms[i]), int(tors[i]), c["n_types"]) for i in range(m)]
+    first = c.get("first_id", 0)
+    args = [(seed, first + i, int(atoms[i]), int(tors[i]), c["n_types"]) for i in range(m)]
     if workers <= 1 or m < 64:
         return [make_ligand(*a) for a in args]
     from concurrent.futures import ProcessPoolExecutor

@@ -179,6 +179,27 @@ def test_training_reduces_loss(dk):
     assert L[-8:].mean() < 0.3 * L[:8].mean(), (L[:8], L[-8:])
 
 
+def test_train_row_order(dk):
+    """A step on rows order[0 .. batch) equals a step on those rows stored contiguously;
+    an index outside the data set is rejected before any kernel runs."""
+    flat, _ = rand_params(61)
+    x = rand_x(62, 512)
+    t = np.random.default_rng(63).uniform(-1, 1, (512, 32)).astype(np.float32)
+    order = np.concatenate([np.arange(256, 512), np.arange(0, 256)]).astype(np.int32)
+    a = net_with(dk, flat)
+    dk.dock_mlp_train(a, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), batch=256, n_steps=1, lr=1e-3,
+                      order=torch.from_numpy(order).cuda())
+    b = net_with(dk, flat)
+    dk.dock_mlp_train(b, torch.from_numpy(x[256:].copy()).cuda(), torch.from_numpy(t[256:].copy()).cuda(),
+                      batch=256, n_steps=1, lr=1e-3)
+    np.testing.assert_array_equal(dk.dock_mlp_get_params(a), dk.dock_mlp_get_params(b))
+    bad = order.copy()
+    bad[3] = 512
+    with pytest.raises(dk.DockError):
+        dk.dock_mlp_train(a, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), batch=256, n_steps=1,
+                          lr=1e-3, order=torch.from_numpy(bad).cuda())
+
+
 def test_train_rejects_bad_shapes(dk):
     net = dk.dock_mlp_create(0, 1)
     x = torch.zeros((100, 96), dtype=torch.float32, device="cuda")
@@ -382,6 +403,20 @@ def test_learned_search_rounds_and_stop(dk, learn_sys):
     b = run(-1e30, 0)
     for u, v in zip(a, b):
         np.testing.assert_array_equal(u, v)        # deterministic
+    # the same search as resumed pieces (cut inside and on round generations) is identical
+    popu = torch.zeros((nl, pop, stride), dtype=torch.float32, device="cuda")
+    pe = torch.zeros((nl, pop), dtype=torch.float32, device="cuda")
+    bg = torch.zeros((nl, stride), dtype=torch.float32, device="cuda")
+    be = torch.zeros(nl, dtype=torch.float32, device="cuda")
+    tg = torch.full((nl,), -1e30, dtype=torch.float32, device="cuda")
+    gr = torch.zeros(nl, dtype=torch.int32, device="cuda")
+    for g0, g1 in ((0, 7), (7, 20), (20, 30)):
+        p = dk.SearchParams(pop_size=pop, n_generations=g1 - g0, seed=2, box_lo=tuple(S["lo"]),
+                            box_hi=tuple(S["hi"]), proposal=net, proposal_step=0.5, proposal_every=10,
+                            proposal_until=25, init=int(g0 == 0), first_generation=g0)
+        dk.dock_search(S["pocket"], S["L"], p, popu, pe, bg, be, target=tg, gen_reached=gr)
+    np.testing.assert_array_equal(popu.cpu().numpy(), a[0])
+    np.testing.assert_array_equal(be.cpu().numpy(), a[2])
     assert np.all(a[3] == -1)
     for li, lg in enumerate(S["ligs"]):
         e = oracle.score_poses(S["grid"], S["maps"], S["ff"], [lg], a[0][li])

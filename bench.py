@@ -7,7 +7,11 @@ Genotypes (680 MB) and maps are resident in HBM before timing starts.
 
 Prints one JSON line: throughput in poses/s, the scoring kernel against its
 roofline (kernel time from HIP events on the launch stream), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Beside them (unless
+--no-search): the persistent search's throughput on the 1000- and
+10000-ligand batches, and time-to-target of the plain and the learned search
+on the 10000-ligand batch, with the learned proposal trained first on plain
+runs over 5000 other ligands.
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ METRIC = "poses scored/sec (FP32, vs FP64 oracle) + time-to-target score, plain 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# Algorithmic work per pose, see the design doc (measurement section)
+# Algorithmic work per pose
 BYTES_PER_ATOM = 96            # 3 maps x 8 corners x 4 B gathered per atom
 FLOPS_PER_PAIR = 38            # one 12-6 pair term (FMA = 2, transcendental = 1)
 
@@ -153,6 +157,123 @@ def cpu_baseline(S, target_seconds: float, max_poses: int):
             "sample": f"first {n} of the 1e7 genotypes, scored in {t:.1f} s (FP64, {threads} threads)"}
 
 
+def batch_setup(cfg_id: int, extra_cfg: int | None = None):
+    """Pocket (GPU-built maps) and ligand set(s) of a batch workload."""
+    from paper_2509_12232_amd import dock as dk
+    c = synth.CONFIGS[cfg_id]
+    nt = c["n_types"]
+    ff = synth.forcefield(nt)
+    rec = synth.make_receptor(1, 2000, nt)
+    grid = synth.make_grid(c["grid_n"], nt)
+    pocket = dk.dock_create_pocket_from_receptor(grid, ff, rec, device=0)
+    ligands = synth.config_ligands(cfg_id, workers=16)
+    sets = [ligands] + ([synth.config_ligands(extra_cfg, workers=16)] if extra_cfg is not None else [])
+    handles = [dk.dock_create_ligands(pocket, s) for s in sets]
+    stride = 7 + max(lg.n_torsions for s in sets for lg in s)
+    lo, hi = synth.pocket_box(grid)
+    return dict(dk=dk, pocket=pocket, sets=sets, handles=handles, stride=stride, lo=tuple(lo), hi=tuple(hi), c=c)
+
+
+def search_throughput(B, gens: int, pop: int):
+    """One plain search over the whole batch (fresh population, `gens`
+    generations) after a 2-generation warm-up: poses scored per second of wall
+    time (pop x (gens + 1) poses per ligand)."""
+    import torch
+    from paper_2509_12232_amd import proposal as pr
+    dk = B["dk"]
+    L = B["handles"][0]
+    buf = pr._buffers(L.n, pop, B["stride"])
+    p = dk.SearchParams(pop_size=pop, n_generations=2, seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
+    torch.cuda.synchronize()
+    p = dk.SearchParams(pop_size=pop, n_generations=gens, seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    t0 = time.perf_counter()
+    dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = L.n * pop * (gens + 1)
+    return {"ligands": L.n, "pop": pop, "generations": gens, "seconds": round(dt, 4),
+            "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4)}
+
+
+def learned_vs_plain():
+    """Time-to-target on the 10000-ligand batch, plain DE vs the learned proposal.
+
+    The network is trained (on the GPU, by the library's kernels) on plain runs
+    over 5000 other ligands.  Batch level: GPU time until the median best energy
+    over the batch reaches the plain search's final median + 0.1 kcal/mol.
+    Ligand level: the fraction of ligands whose best reaches the plain (seed 1)
+    final best + 0.1, and the generations it took; a plain run with another
+    seed is the baseline for that fraction (the seed-1 plain run reaches every
+    target by construction)."""
+    import torch
+    from paper_2509_12232_amd import proposal as pr
+    B = batch_setup(3, extra_cfg=4)
+    dk = B["dk"]
+    c4 = synth.CONFIGS[4]
+    L_ev, L_tr = B["handles"]
+    stride = B["stride"]
+    P = dk.SearchParams(pop_size=c4["pop"], n_generations=c4["gens"], seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    # plain, seed 1: the reference bests and the plain batch-level curve
+    plain_pts, buf = pr.anytime(B["pocket"], L_ev, P, stride)
+    ref_best = buf["be"].cpu().numpy()
+    level = float(np.median(ref_best)) + 0.1
+    target = buf["be"] + 0.1
+    # training data and training
+    t0 = time.perf_counter()
+    snaps, fin = pr.plain_snapshots(B["pocket"], L_tr, P, stride, pr.SNAPSHOT_GENERATIONS)
+    x, t = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
+    del snaps
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cfg = pr.TrainConfig(n_tuples=c4["tuples"])
+    net, losses = pr.train(x, t, cfg)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    n_tuples_avail = int(x.shape[0])
+    del x, t
+    prop = pr.ProposalConfig()
+    learned_pts, lbuf = pr.anytime(B["pocket"], L_ev, P, stride, net, prop, reference_best=ref_best)
+    from dataclasses import replace
+    plain2_pts, _ = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, reference_best=ref_best)
+    # ligand level, with every ligand stopping at its target
+    stops = {"plain_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target),
+             "plain_seed2": pr.time_to_target(B["pocket"], L_ev, replace(P, seed=2), stride, target),
+             "learned_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target, net, prop)}
+
+    def lig_stats(r):
+        g = r["gen_reached"]
+        ok = g >= 0
+        return {"gpu_ms": round(r["ms"], 1), "reached": round(float(ok.mean()), 4),
+                "gen_median": float(np.median(g[ok])) if ok.any() else None,
+                "gen_p90": float(np.percentile(g[ok], 90)) if ok.any() else None}
+
+    tp_ms, tp_gen = pr.time_to_level(plain_pts, level)
+    tl_ms, tl_gen = pr.time_to_level(learned_pts, level)
+    t2_ms, t2_gen = pr.time_to_level(plain2_pts, level)
+    rnd = (lambda v: None if v is None else round(v, 1))
+    return {
+        "workload": f"{L_ev.n} ligands (atoms lognormal median 32, 8-96; 0-20 torsions), 14 fp32 maps at 80^3, "
+                    f"DE pop {P.pop_size} x {P.n_generations} generations",
+        "level": round(level, 4),
+        "batch_time_to_level_ms": {"plain_seed1": rnd(tp_ms), "plain_seed2": rnd(t2_ms), "learned_seed1": rnd(tl_ms)},
+        "batch_generations_to_level": {"plain_seed1": rnd(tp_gen), "plain_seed2": rnd(t2_gen),
+                                       "learned_seed1": rnd(tl_gen)},
+        "speedup_vs_plain_seed1": round(tp_ms / tl_ms, 3) if tp_ms and tl_ms else None,
+        "median_best_at_end": {"plain_seed1": round(plain_pts[-1][2], 4), "plain_seed2": round(plain2_pts[-1][2], 4),
+                               "learned_seed1": round(learned_pts[-1][2], 4)},
+        "gpu_ms_at_end": {"plain_seed1": round(plain_pts[-1][1], 1), "plain_seed2": round(plain2_pts[-1][1], 1),
+                          "learned_seed1": round(learned_pts[-1][1], 1)},
+        "ligand_targets": {k: lig_stats(v) for k, v in stops.items()},
+        "proposal": {"step": prop.step, "every": prop.every, "until": prop.until},
+        "training": {"ligands": L_tr.n, "tuples_available": n_tuples_avail, "tuples": cfg.n_tuples,
+                     "steps": int(len(losses)), "batch": cfg.batch, "lr": cfg.lr,
+                     "loss_first": round(float(losses[:10].mean()), 4), "loss_last": round(float(losses[-50:].mean()), 4),
+                     "data_s": round(data_s, 2), "train_s": round(train_s, 2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,13 +282,15 @@ def main():
     ap.add_argument("--poses", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-search", action="store_true", help="skip the search and learned-proposal legs")
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: one 1 GiB device copy (calibration of the "
                          "FETCH_SIZE/WRITE_SIZE counters) and two scoring steps, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the workload shards by pose range "
-              "across GPUs with no communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the scoring workload would shard by "
+              "pose range and the searches by ligand, with no communication inside the timed work",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -233,6 +356,17 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(S, args.cpu_seconds, n)
+    if not args.no_search:
+        del S
+        torch.cuda.empty_cache()
+        searches = {}
+        for cid in (2, 3):
+            c = synth.CONFIGS[cid]
+            log(f"search throughput on the {c['n_ligands']}-ligand batch")
+            searches[f"{c['n_ligands']}_ligands"] = search_throughput(batch_setup(cid), c["gens"], c["pop"])
+        out["search"] = searches
+        log("learned proposal vs plain DE")
+        out["time_to_target"] = learned_vs_plain()
     print(json.dumps(out), flush=True)
 
 

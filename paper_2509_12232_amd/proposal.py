@@ -9,12 +9,15 @@ buffers:
   at chosen generations and the final one;
 * ``make_tuples`` -- for every individual of every snapshot, the network input
   (its genotype and its ligand's descriptor) and, as target, the encoded move
-  from it to the same individual of the final population: the accepted moves
-  the plain search made from there on, composed;
+  from it to the converged pose the plain search reached for that ligand (or,
+  optionally, to the same individual of the final population: the accepted
+  moves of that individual from there on, composed);
 * ``train`` -- Adam on minibatches of a seeded random sample of those tuples;
 * ``time_to_target`` -- one search (plain or learned) in which every ligand
   stops once its population best reaches its target, timed with HIP events on
-  the launching stream.
+  the launching stream;
+* ``anytime`` / ``time_to_level`` -- the median best energy of a batch against
+  GPU time, and the time at which it first reaches a level.
 """
 from __future__ import annotations
 
@@ -52,10 +55,18 @@ def plain_snapshots(pocket, ligs, params: dk.SearchParams, stride: int, snap_gen
     return snaps, B
 
 
-def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop):
-    """(x [N, 96], target [N, 32]) for every individual of every snapshot."""
+SNAPSHOT_GENERATIONS = (0, 5, 15, 40, 80)
+
+
+def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop=None, final_best=None):
+    """(x [N, 96], target [N, 32]) for every individual of every snapshot: the
+    target is the encoded move to the ligand's converged pose (final_best
+    [n_ligs][g_stride], the best member of the final population) or, given
+    final_pop instead, to the same individual of the final population."""
     import torch
     n = ligs.n * params.pop_size
+    if final_best is not None:
+        final_pop = final_best[:, None, :].expand(-1, params.pop_size, -1).contiguous()
     xs, ts = [], []
     for g in sorted(snaps):
         x = torch.empty((n, dk.DOCK_MLP_IN), dtype=torch.float32, device="cuda")
@@ -71,7 +82,7 @@ def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop):
 class TrainConfig:
     n_tuples: int = 1_000_000   # size of the random sample trained on
     batch: int = 4096
-    epochs: float = 4.0
+    epochs: float = 8.0
     lr: float = 1e-3
     seed: int = 1
 
@@ -96,8 +107,8 @@ def train(x, t, cfg: TrainConfig):
 @dataclass
 class ProposalConfig:
     step: float = 1.0     # alpha_max
-    every: int = 0        # learned round every this many generations (0: only after the initial population)
-    until: int = 1 << 30  # no later rounds at or after this generation
+    every: int = 5        # learned round every this many generations (0: only after the initial population)
+    until: int = 100      # no later rounds at or after this generation
 
 
 def time_to_target(pocket, ligs, params: dk.SearchParams, stride: int, target, net=None,
@@ -120,3 +131,45 @@ def time_to_target(pocket, ligs, params: dk.SearchParams, stride: int, target, n
     b.record()
     torch.cuda.synchronize()
     return dict(ms=a.elapsed_time(b), gen_reached=gr.cpu().numpy(), best=B["be"].cpu().numpy())
+
+
+def anytime(pocket, ligs, params: dk.SearchParams, stride: int, net=None, prop: ProposalConfig | None = None,
+            seg: int = 10, reference_best=None):
+    """A search of params.n_generations generations from a fresh population, run
+    as resumed pieces of `seg` generations (the same search as one call).  After
+    each piece: (generations, cumulative GPU ms from HIP events on the current
+    stream, median best energy over the ligands, fraction of ligands whose best
+    is <= reference_best + 0.1 (a host array; None: nan))."""
+    import torch
+    prop = prop or ProposalConfig()
+    B = _buffers(ligs.n, params.pop_size, stride)
+    pts, cum = [], 0.0
+    for g0 in range(0, params.n_generations, seg):
+        n = min(seg, params.n_generations - g0)
+        p = replace(params, init=int(g0 == 0), first_generation=g0, n_generations=n, proposal=net,
+                    proposal_step=prop.step, proposal_every=prop.every, proposal_until=prop.until,
+                    stop_at_target=0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        dk.dock_search(pocket, ligs, p, B["pop"], B["pe"], B["bg"], B["be"])
+        b.record()
+        torch.cuda.synchronize()
+        cum += a.elapsed_time(b)
+        be = B["be"].cpu().numpy()
+        frac = float(np.mean(be <= reference_best + 0.1)) if reference_best is not None else float("nan")
+        pts.append((g0 + n, cum, float(np.median(be)), frac))
+    return pts, B
+
+
+def time_to_level(pts, level: float):
+    """(GPU ms, generations) at which the median best of an anytime curve first
+    reaches `level`, interpolated linearly inside the piece; (None, None) if never."""
+    prev = (0, 0.0, float("inf"))
+    for g, ms, med, _ in pts:
+        if med <= level:
+            g0, ms0, m0 = prev
+            f = (m0 - level) / (m0 - med) if np.isfinite(m0) and m0 > med else 1.0
+            return ms0 + f * (ms - ms0), g0 + f * (g - g0)
+        prev = (g, ms, med)
+    return None, None

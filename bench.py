@@ -176,14 +176,17 @@ def batch_setup(cfg_id: int, extra_cfg: int | None = None):
 
 def search_throughput(B, gens: int, pop: int):
     """One plain search over the whole batch (fresh population, `gens`
-    generations) after a 2-generation warm-up: poses scored per second of wall
-    time (pop x (gens + 1) poses per ligand)."""
+    generations) after the launch-shape autotuner and a 2-generation warm-up:
+    poses scored per second of wall time (pop x (gens + 1) poses per ligand)."""
     import torch
     from paper_2509_12232_amd import proposal as pr
     dk = B["dk"]
     L = B["handles"][0]
     buf = pr._buffers(L.n, pop, B["stride"])
     p = dk.SearchParams(pop_size=pop, n_generations=2, seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    t0 = time.perf_counter()
+    dk.dock_search_autotune(B["pocket"], L, p, B["stride"], tune_generations=3)
+    tune_s = time.perf_counter() - t0
     dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
     torch.cuda.synchronize()
     p = dk.SearchParams(pop_size=pop, n_generations=gens, seed=1, box_lo=B["lo"], box_hi=B["hi"])
@@ -192,8 +195,10 @@ def search_throughput(B, gens: int, pop: int):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n = L.n * pop * (gens + 1)
+    shapes = {f"<={b}": {"lanes_per_pose": lp, "waves": w} for b, lp, w in dk.dock_search_shapes(L)}
     return {"ligands": L.n, "pop": pop, "generations": gens, "seconds": round(dt, 4),
-            "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4)}
+            "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4),
+            "autotune_s": round(tune_s, 2), "shapes": shapes}
 
 
 def learned_vs_plain():
@@ -214,6 +219,8 @@ def learned_vs_plain():
     L_ev, L_tr = B["handles"]
     stride = B["stride"]
     P = dk.SearchParams(pop_size=c4["pop"], n_generations=c4["gens"], seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    for L in (L_ev, L_tr):
+        dk.dock_search_autotune(B["pocket"], L, P, stride, tune_generations=3)
     # plain, seed 1: the reference bests and the plain batch-level curve
     plain_pts, buf = pr.anytime(B["pocket"], L_ev, P, stride)
     ref_best = buf["be"].cpu().numpy()

@@ -228,6 +228,38 @@ dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, con
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);
 
+/* ---- Launch shapes of the search and their autotuner --------------------------
+ * dock_search runs one persistent kernel per ligand-size bucket (atom counts
+ * up to 16, 32, 48, 64, 96).  Its shape: lanes per pose (1: each lane builds
+ * and scores a pose; 2: two lanes share a pose, splitting its atoms and pair
+ * records, which halves the LDS per wavefront) and wavefronts per workgroup (1-4,
+ * 0 = chosen at launch from the ligand count and the LDS residency).  Energies,
+ * and hence search results, do not depend on the shape: both forms sum the
+ * same partial sums in the same order.  Shapes are launch configuration kept in
+ * the ligand handle (the one exception to its immutability): set or tune them
+ * while no search on the handle is in flight. */
+#define DOCK_SEARCH_BUCKETS 5
+typedef struct {
+  int32_t max_atoms;        /* the bucket's upper atom count (read-only: 16, 32, 48, 64, 96) */
+  int32_t lanes_per_pose;   /* 1 or 2 */
+  int32_t waves_per_group;  /* 0..4 */
+} dock_search_shape;
+
+/* Current shapes, host dock_search_shape[DOCK_SEARCH_BUCKETS]. */
+dock_status dock_search_shapes(const dock_ligands *ligs, dock_search_shape *shapes);
+/* Fixes the shapes (host array as above; max_atoms must match). */
+dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *shapes);
+/* Autotuner: for every non-empty bucket, times a search of tune_generations
+ * generations (params' pop_size, seed, box) of the bucket's ligands for every
+ * shape (1 and 2 lanes per pose x 1 up to 4 wavefronts), warm-up run first,
+ * with HIP events on stream, and fixes the fastest.  Results are cached for the
+ * process under (device, map layout and dimensions, bucket, its largest ligand,
+ * pop_size); a cached bucket is not timed again, and dock_search uses cached
+ * shapes for handles whose shapes were not fixed.  Synchronous; allocates and
+ * frees its own scratch state; 1 <= tune_generations <= 1000. */
+dock_status dock_search_autotune(const dock_pocket *pocket, dock_ligands *ligs, const dock_search_params *params,
+                                 int32_t g_stride, int32_t tune_generations, void *stream);
+
 /* ---- Learned proposal --------------------------------------------------------
  * An addition to the paper's method (whose search, Sec. V, has no learned
  * part): a perceptron 96 -> 256 -> 256 -> 32 with ReLU hidden layers proposes

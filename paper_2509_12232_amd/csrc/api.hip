@@ -6,7 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <numeric>
 #include <vector>
 
@@ -521,7 +523,9 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
     });
     int mx = 1;
     for (int32_t l : ids) mx = std::max(mx, hdr[l].n_atoms);
-    L->buckets.push_back(LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size()});
+    // default shape (until tuned or set): two lanes per pose once the LDS of a
+    // lane's coordinates limits residency
+    L->buckets.push_back(LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size(), mx > 16 ? 2 : 1, 0, 0});
     order.insert(order.end(), ids.begin(), ids.end());
     lo = ub;
   }
@@ -647,6 +651,39 @@ extern "C" dock_status dock_de_trials(const dock_ligands *L, const dock_search_p
   return DOCK_OK;
 }
 
+// ------------------------------------------------------------------------------ search shapes
+namespace {
+
+// Launch shapes found by the autotuner, for the whole process, keyed by what
+// decides them: device, map layout and size, the bucket and its largest ligand,
+// the population size.
+struct ShapeKey {
+  int device, layout, nx, ny, nz, n_types, upper, lds_atoms, pop;
+  bool operator<(const ShapeKey &o) const {
+    return std::tie(device, layout, nx, ny, nz, n_types, upper, lds_atoms, pop) <
+           std::tie(o.device, o.layout, o.nx, o.ny, o.nz, o.n_types, o.upper, o.lds_atoms, o.pop);
+  }
+};
+std::mutex g_shape_mu;
+std::map<ShapeKey, SearchShape> g_shapes;
+
+ShapeKey shape_key(const dock_pocket *p, const LigandBucket &B, int pop) {
+  return ShapeKey{p->device, p->layout, p->geom.nx, p->geom.ny, p->geom.nz, p->geom.n_types, B.upper, B.lds_atoms, pop};
+}
+
+}  // namespace
+
+// The shape a bucket's search launch uses: the one set on the handle, else a
+// tuned one for the same key, else the bucket's default.
+static SearchShape bucket_shape(const dock_pocket *p, const LigandBucket &B, int pop) {
+  if (!B.fixed) {
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    auto it = g_shapes.find(shape_key(p, B, pop));
+    if (it != g_shapes.end()) return it->second;
+  }
+  return SearchShape{B.lanes_per_pose, B.waves};
+}
+
 // One pass of the persistent search kernels over every size bucket, generations
 // [S.p.first_gen, S.p.first_gen + S.p.n_gen): the buckets run concurrently on the
 // handle's side streams (forked from and joined back to s), so that small
@@ -673,7 +710,7 @@ static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, Searc
     S.n_order = B.count;
     S.queue = queues + b;
     S.lds_atoms = B.lds_atoms;
-    if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, side, step);
+    if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, bucket_shape(p, B, S.p.pop), side, step);
     hipEvent_t done = nullptr;
     if (e == hipSuccess) *step = "side streams", e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
     if (e == hipSuccess) {
@@ -732,6 +769,7 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   int32_t *queues = nullptr;
   const char *step = "search buffers";
   hipError_t e = hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&S.work, sizeof(float) * n * g_stride, s);
   if (e == hipSuccess) e = hipMallocAsync((void **)&queues, sizeof(int32_t) * L->buckets.size(), s);
   if (e == hipSuccess && !net) {
     e = search_pass(p, L, S, queues, s, &step);
@@ -782,7 +820,131 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
     }
   }
   if (queues) (void)hipFreeAsync(queues, s);
+  if (S.work) (void)hipFreeAsync(S.work, s);
   if (S.trials) (void)hipFreeAsync(S.trials, s);
+  if (e != hipSuccess) return hip_err(e, step);
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ shapes and autotuner
+extern "C" dock_status dock_search_shapes(const dock_ligands *L, dock_search_shape *shapes) {
+  if (!L || !shapes) return set_err(DOCK_E_INVALID, "null argument");
+  for (size_t b = 0; b < L->buckets.size(); ++b)
+    shapes[b] = dock_search_shape{L->buckets[b].upper, L->buckets[b].lanes_per_pose, L->buckets[b].waves};
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search_set_shapes(dock_ligands *L, const dock_search_shape *shapes) {
+  if (!L || !shapes) return set_err(DOCK_E_INVALID, "null argument");
+  for (size_t b = 0; b < L->buckets.size(); ++b) {
+    const dock_search_shape &x = shapes[b];
+    if (x.max_atoms != L->buckets[b].upper) return set_err(DOCK_E_INVALID, "bucket %d bound must be %d", (int)b, L->buckets[b].upper);
+    if (x.lanes_per_pose != 1 && x.lanes_per_pose != 2) return set_err(DOCK_E_INVALID, "lanes_per_pose must be 1 or 2");
+    if (x.waves_per_group < 0 || x.waves_per_group > kSearchMaxThreads / kWave)
+      return set_err(DOCK_E_INVALID, "waves_per_group must be in 0..%d", kSearchMaxThreads / kWave);
+  }
+  std::lock_guard<std::mutex> guard(L->side_mu);
+  for (size_t b = 0; b < L->buckets.size(); ++b) {
+    L->buckets[b].lanes_per_pose = shapes[b].lanes_per_pose;
+    L->buckets[b].waves = shapes[b].waves_per_group;
+    L->buckets[b].fixed = 1;
+  }
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *L, const dock_search_params *q,
+                                            int32_t g_stride, int32_t tune_generations, void *stream) {
+  dock_status st = check_pair(p, L);
+  if (st) return st;
+  if ((st = check_params(q))) return st;
+  if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
+  if (tune_generations < 1 || tune_generations > 1000) return set_err(DOCK_E_INVALID, "tune_generations must be in 1..1000");
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int P = q->pop_size;
+  const int64_t n = (int64_t)L->n_ligs * P;
+  // scratch state of a search over the whole set (the timed runs touch one bucket each)
+  SearchLaunch S{};
+  S.L = L->view();
+  S.geom = p->geom;
+  S.ff = p->ffc;
+  S.maps = p->view();
+  S.p = de_params(q);
+  S.p.first_gen = 0;
+  S.p.n_gen = tune_generations;
+  S.g_stride = g_stride;
+  S.init = 1;
+  float *buf = nullptr;
+  int32_t *queue = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  const char *step = "autotune buffers";
+  const size_t nf = (size_t)n * g_stride;
+  hipError_t e = hipMalloc((void **)&buf, sizeof(float) * (3 * nf + n + (size_t)L->n_ligs * (g_stride + 1)));
+  if (e == hipSuccess) e = hipMalloc((void **)&queue, sizeof(int32_t));
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e == hipSuccess) {
+    S.population = buf;
+    S.trials = buf + nf;
+    S.work = buf + 2 * nf;
+    S.pop_energy = buf + 3 * nf;
+    S.best_g = S.pop_energy + n;
+    S.best_e = S.best_g + (size_t)L->n_ligs * g_stride;
+  }
+  for (size_t b = 0; b < L->buckets.size() && e == hipSuccess; ++b) {
+    LigandBucket &B = L->buckets[b];
+    if (B.count == 0) continue;
+    {
+      std::lock_guard<std::mutex> g(g_shape_mu);
+      auto it = g_shapes.find(shape_key(p, B, P));
+      if (it != g_shapes.end()) {
+        B.lanes_per_pose = it->second.lanes_per_pose, B.waves = it->second.waves, B.fixed = 1;
+        continue;
+      }
+    }
+    S.order = L->order + B.offset;
+    S.n_order = B.count;
+    S.queue = queue;
+    S.lds_atoms = B.lds_atoms;
+    SearchShape best{0, 0};
+    float best_ms = 0.f;
+    for (int lp = 1; lp <= 2 && e == hipSuccess; ++lp) {
+      const int max_w = std::min(kSearchMaxThreads / kWave, (P * lp + kWave - 1) / kWave);
+      for (int w = 1; w <= max_w && e == hipSuccess; ++w) {
+        const SearchShape shape{lp, w};
+        if (!search_shape_fits(B.lds_atoms, shape)) continue;
+        float ms = 0.f;
+        // a warm-up run, then the timed one
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+          step = "autotune run";
+          e = launch_fill_i32(queue, 1, 0, s);
+          if (e == hipSuccess) e = hipEventRecord(t0, s);
+          if (e == hipSuccess) e = launch_search(S, p->layout, p->n_cu, shape, s, &step);
+          if (e == hipErrorInvalidConfiguration) {  // this shape does not fit the CU: skip it
+            (void)hipGetLastError();
+            e = hipSuccess;
+            ms = -1.f;
+            break;
+          }
+          if (e == hipSuccess) e = hipEventRecord(t1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(t1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        }
+        if (e == hipSuccess && ms >= 0.f && (best.lanes_per_pose == 0 || ms < best_ms)) best = shape, best_ms = ms;
+      }
+    }
+    if (e != hipSuccess || best.lanes_per_pose == 0) break;
+    B.lanes_per_pose = best.lanes_per_pose;
+    B.waves = best.waves;
+    B.fixed = 1;
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    g_shapes[shape_key(p, B, P)] = best;
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (queue) (void)hipFree(queue);
+  if (buf) (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(e, step);
   return DOCK_OK;
 }

@@ -121,13 +121,16 @@ __global__ void reduce_partial_kernel(const float *partial, int chunks, int n, f
   out[i] = s;
 }
 
-// out[c] = sum over rows of Z[m][c] (row order)
-__global__ void colsum_kernel(const bf16 *Z, int64_t mp, int N, float *out) {
+// partial[chunk][c] = sum over the rows m of the chunk of Z[m][c] (row order);
+// neighbouring threads read neighbouring columns of a row
+__global__ void colsum_partial_kernel(const bf16 *Z, int64_t mp, int N, float *partial) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
+  const int64_t m0 = (int64_t)blockIdx.y * kWgradChunk;
+  const int64_t m1 = m0 + kWgradChunk < mp ? m0 + kWgradChunk : mp;
   float s = 0.f;
-  for (int64_t m = 0; m < mp; ++m) s += (float)Z[m * N + c];
-  out[c] = s;
+  for (int64_t m = m0; m < m1; ++m) s += (float)Z[m * N + c];
+  partial[(int64_t)blockIdx.y * N + c] = s;
 }
 
 // ------------------------------------------------------------ input, loss, Adam
@@ -467,8 +470,15 @@ static hipError_t wgrad(const bf16 *Xp8, const bf16 *Zp8, int64_t mp, int K, int
   return hipGetLastError();
 }
 
-static hipError_t colsum(const bf16 *Z, int64_t mp, int N, float *out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(N, 64)), dim3(64), 0, s, Z, mp, N, out);
+// out[c] = column sums of Z, by chunks of kWgradChunk rows summed in chunk order
+// (partial needs ceil(mp / kWgradChunk) * N floats)
+static hipError_t colsum(const bf16 *Z, int64_t mp, int N, float *partial, float *out, hipStream_t s) {
+  const int chunks = (int)((mp + kWgradChunk - 1) / kWgradChunk);
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks_for(N, 64), chunks), dim3(64), 0, s, Z, mp, N, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, (const float *)partial,
+                     chunks, N, out);
   return hipGetLastError();
 }
 
@@ -514,7 +524,7 @@ hipError_t launch_mlp_backward(const MlpWeights &W, const MlpActs &A, const MlpG
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // layer 3
   if ((e = wgrad(A.a2p8, G.g3p8, mp, kMlpHidden, kMlpOut, G.partial, G.grads + kOffW3, s)) != hipSuccess) return e;
-  if ((e = colsum(G.g3, mp, kMlpOut, G.grads + kOffB3, s)) != hipSuccess) return e;
+  if ((e = colsum(G.g3, mp, kMlpOut, G.partial, G.grads + kOffB3, s)) != hipSuccess) return e;
   GemmRK g{};
   g.mp = mp;
   g.A = G.g3, g.Bt = W.wr3, g.N = kMlpHidden, g.K = kMlpOut, g.mask = A.a2, g.out = G.g2, g.out_p8 = G.g2p8;
@@ -522,12 +532,12 @@ hipError_t launch_mlp_backward(const MlpWeights &W, const MlpActs &A, const MlpG
   // layer 2
   if ((e = wgrad(A.a1p8, G.g2p8, mp, kMlpHidden, kMlpHidden, G.partial, G.grads + kOffW2, s)) != hipSuccess)
     return e;
-  if ((e = colsum(G.g2, mp, kMlpHidden, G.grads + kOffB2, s)) != hipSuccess) return e;
+  if ((e = colsum(G.g2, mp, kMlpHidden, G.partial, G.grads + kOffB2, s)) != hipSuccess) return e;
   g.A = G.g2, g.Bt = W.wr2, g.N = kMlpHidden, g.K = kMlpHidden, g.mask = A.a1, g.out = G.g1, g.out_p8 = G.g1p8;
   if ((e = gemm_rk<kEpiMask>(g, s)) != hipSuccess) return e;
   // layer 1
   if ((e = wgrad(A.a0p8, G.g1p8, mp, kMlpIn, kMlpHidden, G.partial, G.grads + kOffW1, s)) != hipSuccess) return e;
-  return colsum(G.g1, mp, kMlpHidden, G.grads + kOffB1, s);
+  return colsum(G.g1, mp, kMlpHidden, G.partial, G.grads + kOffB1, s);
 }
 
 hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grads, const AdamStep &a, bf16 *wt1,

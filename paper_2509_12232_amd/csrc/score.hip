@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
     const LigHeader H = A.L.hdr[cur];
-    if (valid && lig == cur) e = score_pose<kWave, LAYOUT>(A.L, A.geom, A.ff, A.maps, H, g, my);
+    if (valid && lig == cur) e = score_pose<kWave, LAYOUT>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
     todo &= ~__ballot(valid && lig == cur);
   }
   A.energies[pose] = e;

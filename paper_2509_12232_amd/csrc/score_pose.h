@@ -1,12 +1,13 @@
 // score_pose.h -- device code that builds one pose from its genotype and scores
-// it (Sec. V: Algorithm 1 followed by Algorithm 2), one pose per lane.
+// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one or two lanes per
+// pose.
 //
-// Mapping: every lane owns one pose.  All ligand data (atoms, torsions, pairs)
-// is uniform across the wavefront and arrives through scalar loads, so every
-// loop below is a scalar loop with no divergence.  Each lane keeps its pose's
-// atom coordinates in its own LDS column: coordinate c of atom i at
-// my[(3 i + c) * STRIDE], STRIDE = lanes sharing one LDS row, which makes every
-// LDS access of a wavefront hit 64 consecutive dwords (no bank conflicts).
+// Mapping: a lane (or a pair of lanes in the two halves of a wavefront) owns a
+// pose.  All ligand data (atoms, torsions, pairs) is uniform across the
+// wavefront and arrives through scalar loads, so every loop below is a scalar
+// loop.  The pose's atom coordinates live in an LDS column: coordinate c of
+// atom i at my[(3 i + c) * STRIDE], STRIDE = poses sharing one LDS row, which
+// makes every LDS access of a wavefront hit consecutive dwords.
 #pragma once
 #include "dock_internal.h"
 
@@ -187,31 +188,79 @@ struct GroupCoords {
       xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
     }
   }
-  __device__ __forceinline__ float energy(const FFConst &F, const PairGroup &G) const {
+  // records 0 + 1 and records 2 + 3 of the group
+  __device__ __forceinline__ void energy(const FFConst &F, const PairGroup &G, float &s01, float &s23) const {
     float e[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) e[u] = pair_term<false>(F, G.r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
-    return (e[0] + e[1]) + (e[2] + e[3]);
+    s01 = e[0] + e[1];
+    s23 = e[2] + e[3];
   }
 };
 
-// Energy of the pose given by genotype row g (per lane) for ligand header H
-// (uniform).  Non-finite genes give NaN.
-template <int STRIDE, int LAYOUT>
+// Coordinates of the two pairs of a group that one lane of a two-lane pose
+// evaluates: records 2 h and 2 h + 1 for the lane's half h.
+template <int STRIDE>
+struct HalfGroupCoords {
+  float xi[2], yi[2], zi[2], xj[2], yj[2], zj[2];
+  PairRec r[2];
+  __device__ __forceinline__ void load(const PairGroup &G, float *my, bool h) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const PairRec &a = G.r[u], &b = G.r[2 + u];
+      r[u].ij = h ? b.ij : a.ij;
+      r[u].A = h ? b.A : a.A;
+      r[u].B = h ? b.B : a.B;
+      r[u].qq = h ? b.qq : a.qq;
+      r[u].sv = h ? b.sv : a.sv;
+      const int i = r[u].ij & 0xffff, j = r[u].ij >> 16;
+      xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
+      xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
+    }
+  }
+  __device__ __forceinline__ float energy(const FFConst &F) const {
+    float e[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) e[u] = pair_term<false>(F, r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
+    return e[0] + e[1];
+  }
+};
+
+// Orders LDS writes of one lane before reads by other lanes of the wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Energy of the pose whose gene j is g[j * gs] for ligand header H (uniform).
+// LP lanes build and score one pose together.  With LP = 2 the lanes of the two
+// halves of the wavefront (h = lane / 32) share the pose's LDS column and split
+// its atoms by parity and every pair group (records 2h and 2h + 1); lanes of one
+// pose exchange coordinates through LDS, ordered by wave_sync().  In both forms
+// the energy is accumulated as
+//   (inter over even atoms + records 0-1 of every group + even 12-10 pairs)
+//   + (inter over odd atoms + records 2-3 of every group + odd 12-10 pairs),
+// each part summed in index order, so LP = 1 and LP = 2 give the same bits.
+// Non-finite genes give NaN.
+template <int STRIDE, int LAYOUT, int LP = 1>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
-                            const LigHeader &H,
-                            const float *__restrict__ g, float *__restrict__ my) {
+                            const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my) {
+  static_assert(LP == 1 || LP == 2, "one or two lanes per pose");
   const int n = H.n_atoms;
   const float4 *__restrict__ atoms = L.atoms + H.atom_off;
   const int32_t *__restrict__ types = L.atom_type + H.atom_off;
+  const int h = LP == 2 ? (int)((threadIdx.x & 63) >> 5) : 0;
+  if (LP == 2) wave_sync();  // the column's previous pose has been read by both lanes
 
-  // reference conformation (centred) into this lane's LDS column
-  for (int i = 0; i < n; ++i) {
+  // reference conformation (centred) into the pose's LDS column
+  for (int i = h; i < n; i += LP) {
     const float4 a = atoms[i];
     at<STRIDE>(my, i, 0) = a.x;
     at<STRIDE>(my, i, 1) = a.y;
     at<STRIDE>(my, i, 2) = a.z;
   }
+  if (LP == 2) wave_sync();
 
   bool bad = false;
   // Algorithm 1, rotatable bonds: rotate each fragment about its current bond
@@ -220,7 +269,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   const TorRec *__restrict__ tors = L.tors + H.tor_off;
   for (int k = 0; k < H.n_tors; ++k) {
     const TorRec T = tors[k];
-    const float th = g[7 + T.gene];
+    const float th = g[(7 + T.gene) * gs];
     bad |= !__builtin_isfinite(th);
     const float ax = at<STRIDE>(my, T.a, 0), ay = at<STRIDE>(my, T.a, 1), az = at<STRIDE>(my, T.a, 2);
     float ux = at<STRIDE>(my, T.lo, 0) - ax, uy = at<STRIDE>(my, T.lo, 1) - ay, uz = at<STRIDE>(my, T.lo, 2) - az;
@@ -232,17 +281,18 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
     const float r00 = fmaf(ux * ux, oc, c), r01 = fmaf(ux * uy, oc, -uz * s), r02 = fmaf(ux * uz, oc, uy * s);
     const float r10 = fmaf(uy * ux, oc, uz * s), r11 = fmaf(uy * uy, oc, c), r12 = fmaf(uy * uz, oc, -ux * s);
     const float r20 = fmaf(uz * ux, oc, -uy * s), r21 = fmaf(uz * uy, oc, ux * s), r22 = fmaf(uz * uz, oc, c);
-    for (int i = T.lo + 1; i < T.hi; ++i) {
+    for (int i = T.lo + 1 + h; i < T.hi; i += LP) {
       const float vx = at<STRIDE>(my, i, 0) - ax, vy = at<STRIDE>(my, i, 1) - ay, vz = at<STRIDE>(my, i, 2) - az;
       at<STRIDE>(my, i, 0) = ax + fmaf(r00, vx, fmaf(r01, vy, r02 * vz));
       at<STRIDE>(my, i, 1) = ay + fmaf(r10, vx, fmaf(r11, vy, r12 * vz));
       at<STRIDE>(my, i, 2) = az + fmaf(r20, vx, fmaf(r21, vy, r22 * vz));
     }
+    if (LP == 2) wave_sync();
   }
 
   // Algorithm 1, rigid part: rotate about the ligand origin, then translate
-  const float tx = g[0], ty = g[1], tz = g[2];
-  float qw = g[3], qx = g[4], qy = g[5], qz = g[6];
+  const float tx = g[0], ty = g[gs], tz = g[2 * gs];
+  float qw = g[3 * gs], qx = g[4 * gs], qy = g[5 * gs], qz = g[6 * gs];
   bad |= !(__builtin_isfinite(tx) & __builtin_isfinite(ty) & __builtin_isfinite(tz) & __builtin_isfinite(qw) &
            __builtin_isfinite(qx) & __builtin_isfinite(qy) & __builtin_isfinite(qz));
   const float nn = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
@@ -256,59 +306,112 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   const float R10 = 2.f * (qx * qy + qw * qz), R11 = 1.f - 2.f * (qx * qx + qz * qz), R12 = 2.f * (qy * qz - qw * qx);
   const float R20 = 2.f * (qx * qz - qw * qy), R21 = 2.f * (qy * qz + qw * qx), R22 = 1.f - 2.f * (qx * qx + qy * qy);
 
-  for (int i = 0; i < n; ++i) {
+  for (int i = h; i < n; i += LP) {
     const float px = at<STRIDE>(my, i, 0), py = at<STRIDE>(my, i, 1), pz = at<STRIDE>(my, i, 2);
     at<STRIDE>(my, i, 0) = fmaf(R00, px, fmaf(R01, py, fmaf(R02, pz, tx)));
     at<STRIDE>(my, i, 1) = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
     at<STRIDE>(my, i, 2) = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
   }
+  if (LP == 2) wave_sync();
 
   // Algorithm 2: the inter-energy loop over atoms and the intra-energy loop over
-  // pairs, interleaved.  Iteration k issues the map loads of atom k+1, then
-  // evaluates the k-th of n equal slices of the pair groups, then interpolates
-  // atom k from the loads issued one iteration earlier, so the pair arithmetic
-  // covers the latency of the gathers.  Within the pair loop, the coordinates
-  // of group g+1 and the records of group g+2 are requested before group g is
-  // evaluated (the list ends with spare zero groups to read past).
+  // pairs, interleaved.  Iteration k issues the map loads of the lane's atom of
+  // slot k+1, then evaluates the k-th of equal slices of the pair groups, then
+  // interpolates the atom of slot k from the loads issued one iteration earlier,
+  // so the pair arithmetic covers the latency of the gathers.  Within the pair
+  // loop, the coordinates of group g+1 and the records of group g+2 are
+  // requested before group g is evaluated (the list ends with spare zero
+  // groups to read past).
   const PairRec *__restrict__ pairs = L.pairs + H.pair_off;
   const int ng = H.n_groups;
-  float inter = 0.f, intra = 0.f;
-  // ring[d] holds the loads of atom k + d; atoms are fetched kGatherAhead slices early
+  const int slots = (n + LP - 1) / LP;   // atoms per lane (the last one may be absent)
+  float inter0 = 0.f, inter1 = 0.f, intra0 = 0.f, intra1 = 0.f;
+  // ring[d] holds the loads of the atom of slot k + d; fetched kGatherAhead slices early
   Corners<LAYOUT> ring[kGatherAhead + 1];
+  auto gather = [&](int slot) {
+    const int i = min(slot * LP + h, n - 1);
+    return gather_corners<LAYOUT>(G, maps, types[i], atoms[i].w, at<STRIDE>(my, i, 0), at<STRIDE>(my, i, 1),
+                                  at<STRIDE>(my, i, 2));
+  };
 #pragma unroll
   for (int d = 0; d < kGatherAhead; ++d)
-    if (d < n)
-      ring[d] = gather_corners<LAYOUT>(G, maps, types[d], atoms[d].w, at<STRIDE>(my, d, 0), at<STRIDE>(my, d, 1),
-                                       at<STRIDE>(my, d, 2));
+    if (d < slots) ring[d] = gather(d);
   PairGroup A, B;
   A.load(pairs);
   B.load(pairs + 4);
-  GroupCoords<STRIDE> X;
-  X.load(A, my);
-  for (int k = 0; k < n; ++k) {
-    const int ka = k + kGatherAhead;
-    if (ka < n)
-      ring[kGatherAhead] = gather_corners<LAYOUT>(G, maps, types[ka], atoms[ka].w, at<STRIDE>(my, ka, 0),
-                                                  at<STRIDE>(my, ka, 1), at<STRIDE>(my, ka, 2));
-    const int g0 = (k * ng) / n, g1 = ((k + 1) * ng) / n;
-    for (int gi = g0; gi < g1; ++gi) {
-      GroupCoords<STRIDE> Xn;
-      Xn.load(B, my);
-      PairGroup C;
-      C.load(pairs + 4 * (gi + 2));
-      intra += X.energy(F, A);
-      A = B;
-      B = C;
-      X = Xn;
-    }
-    inter += interpolate_corners<LAYOUT>(ring[0]);
+  if constexpr (LP == 1) {
+    GroupCoords<STRIDE> X;
+    X.load(A, my);
+    for (int k = 0; k < n; ++k) {
+      const int ka = k + kGatherAhead;
+      if (ka < n) ring[kGatherAhead] = gather(ka);
+      const int g0 = (k * ng) / n, g1 = ((k + 1) * ng) / n;
+      for (int gi = g0; gi < g1; ++gi) {
+        GroupCoords<STRIDE> Xn;
+        Xn.load(B, my);
+        PairGroup C;
+        C.load(pairs + 4 * (gi + 2));
+        float s01, s23;
+        X.energy(F, A, s01, s23);
+        intra0 += s01;
+        intra1 += s23;
+        A = B;
+        B = C;
+        X = Xn;
+      }
+      const float v = interpolate_corners<LAYOUT>(ring[0]);
+      if (k & 1) inter1 += v;
+      else inter0 += v;
 #pragma unroll
-    for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+      for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+    }
+    const PairRec *__restrict__ hb = L.pairs + H.hb_off;
+    for (int p = 0; p < H.n_pairs_hb; ++p) {
+      const float e = pair_energy<true, STRIDE>(F, hb[p], my);
+      if (p & 1) intra1 += e;
+      else intra0 += e;
+    }
+    const float e = (inter0 + intra0) + (inter1 + intra1);
+    return bad ? __builtin_nanf("") : e;
+  } else {
+    HalfGroupCoords<STRIDE> X;
+    X.load(A, my, h);
+    for (int k = 0; k < slots; ++k) {
+      const int ka = k + kGatherAhead;
+      if (ka < slots) ring[kGatherAhead] = gather(ka);
+      const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
+      for (int gi = g0; gi < g1; ++gi) {
+        HalfGroupCoords<STRIDE> Xn;
+        Xn.load(B, my, h);
+        PairGroup C;
+        C.load(pairs + 4 * (gi + 2));
+        intra0 += X.energy(F);
+        A = B;
+        B = C;
+        X = Xn;
+      }
+      const float v = interpolate_corners<LAYOUT>(ring[0]);
+      if (k * 2 + h < n) inter0 += v;
+#pragma unroll
+      for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+    }
+    const PairRec *__restrict__ hb = L.pairs + H.hb_off;
+    const PairRec zero{0, 0.f, 0.f, 0.f, 0.f};
+    for (int p = 0; p < H.n_pairs_hb; p += 2) {
+      const PairRec ra = hb[p], rb = p + 1 < H.n_pairs_hb ? hb[p + 1] : zero;
+      PairRec r;
+      r.ij = h ? rb.ij : ra.ij;
+      r.A = h ? rb.A : ra.A;
+      r.B = h ? rb.B : ra.B;
+      r.qq = h ? rb.qq : ra.qq;
+      r.sv = h ? rb.sv : ra.sv;
+      intra0 += pair_energy<true, STRIDE>(F, r, my);
+    }
+    // this half's part, then the sum of both halves (the same on both lanes)
+    const float part = inter0 + intra0;
+    const float e = part + __shfl_xor(part, 32);
+    return bad ? __builtin_nanf("") : e;
   }
-  const PairRec *__restrict__ hb = L.pairs + H.hb_off;
-  for (int p = 0; p < H.n_pairs_hb; ++p) intra += pair_energy<true, STRIDE>(F, hb[p], my);
-  const float e = inter + intra;
-  return bad ? __builtin_nanf("") : e;
 }
 
 }  // namespace dock

@@ -28,7 +28,8 @@ struct SearchLaunch {
   int32_t init;
   float *population;     // [n_ligs][pop][g_stride], in/out
   float *pop_energy;     // [n_ligs][pop], in/out
-  float *trials;         // [n_ligs][pop][g_stride] scratch
+  float *work;           // [n_ligs][g_stride][pop] scratch: the population, gene-major
+  float *trials;         // [n_ligs][g_stride][pop] scratch (trials, gene-major)
   float *best_g;         // [n_ligs][g_stride]
   float *best_e;         // [n_ligs]
   const float *target;   // [n_ligs] or null
@@ -44,6 +45,16 @@ struct SearchLaunch {
 constexpr int kSearchMaxThreads = 256;      // wavefronts per search workgroup: up to 4
 constexpr size_t kLdsPerCU = 160 * 1024;    // gfx950 LDS per compute unit
 
-hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, hipStream_t s, const char **step);
+// Launch shape of a bucket: 1 or 2 lanes per pose, wavefronts per workgroup
+// (0: chosen from the ligand count and the residency the LDS allows).
+struct SearchShape {
+  int32_t lanes_per_pose;
+  int32_t waves;
+};
+
+hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, SearchShape shape, hipStream_t s,
+                         const char **step);
+// Whether a shape's wavefronts fit one CU's LDS for ligands of up to lds_atoms atoms.
+bool search_shape_fits(int32_t lds_atoms, SearchShape shape);
 
 }  // namespace dock

@@ -20,15 +20,16 @@ namespace dock {
 
 constexpr double kPi = 3.14159265358979323846;
 
-__device__ void init_individual(const DEParams &p, int n_tor, int lig, int i, int g_stride, float *row) {
+// Individual i of the initial population; gene j goes to row[j * gs].
+__device__ void init_individual(const DEParams &p, int n_tor, int lig, int i, int g_stride, float *row, int gs) {
 #pragma clang fp contract(off)
   DrawStream s(p.seed, (uint64_t)i, 0, (uint64_t)lig, kPurposeInit);
-  for (int j = 0; j < g_stride; ++j) row[j] = 0.f;
+  for (int j = 0; j < g_stride; ++j) row[j * gs] = 0.f;
   for (int d = 0; d < 3; ++d) {
     const double u = s.unit();
     const double w = p.hi[d] - p.lo[d];
     const double m = u * w;
-    row[d] = (float)(p.lo[d] + m);
+    row[d * gs] = (float)(p.lo[d] + m);
   }
   // a point uniform in the unit 4-ball (rejection from the cube [-1,1]^4)
   float q0 = 1.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
@@ -44,11 +45,11 @@ __device__ void init_individual(const DEParams &p, int n_tor, int lig, int i, in
       break;
     }
   }
-  row[3] = q0; row[4] = q1; row[5] = q2; row[6] = q3;
+  row[3 * gs] = q0; row[4 * gs] = q1; row[5 * gs] = q2; row[6 * gs] = q3;
   for (int k = 0; k < n_tor; ++k) {
     const double u = s.unit();
     const double m = u * (2.0 * kPi);
-    row[7 + k] = (float)(m - kPi);
+    row[(7 + k) * gs] = (float)(m - kPi);
   }
 }
 
@@ -64,8 +65,10 @@ __device__ __forceinline__ int pick_partner(DrawStream &s, int pop, int t0, int 
   }
 }
 
+// Trial i of generation gen.  Gene j of population row r is pop[r * rs + j * gs];
+// gene j of the trial goes to trial[j * tgs].
 __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen, int i, int g_stride,
-                                 const float *__restrict__ pop, float *__restrict__ trial) {
+                                 const float *__restrict__ pop, int rs, int gs, float *__restrict__ trial, int tgs) {
 #pragma clang fp contract(off)
   const int P = p.pop, n_genes = 7 + n_tor;
   DrawStream s(p.seed, (uint64_t)i, (uint64_t)gen, (uint64_t)lig, kPurposeSelect);
@@ -73,19 +76,19 @@ __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen,
   const int r2 = pick_partner(s, P, i, r1, 0, 2);
   const int r3 = pick_partner(s, P, i, r1, r2, 3);
   const int jrand = s.index(n_genes);
-  const float *xi = pop + (size_t)i * g_stride, *x1 = pop + (size_t)r1 * g_stride;
-  const float *x2 = pop + (size_t)r2 * g_stride, *x3 = pop + (size_t)r3 * g_stride;
+  const float *xi = pop + (size_t)i * rs, *x1 = pop + (size_t)r1 * rs;
+  const float *x2 = pop + (size_t)r2 * rs, *x3 = pop + (size_t)r3 * rs;
   DrawStream c(p.seed, (uint64_t)i, (uint64_t)gen, (uint64_t)lig, kPurposeCross);
   for (int j = 0; j < g_stride; ++j) {
     float v = 0.f;
     if (j < n_genes) {
       const double u = c.unit();
       if (u < (double)p.CR || j == jrand) {
-        const double diff = (double)x2[j] - (double)x3[j];
+        const double diff = (double)x2[j * gs] - (double)x3[j * gs];
         const double step = (double)p.F * diff;
-        v = (float)((double)x1[j] + step);
+        v = (float)((double)x1[j * gs] + step);
       } else {
-        v = xi[j];
+        v = xi[j * gs];
       }
       if (j < 3) {
         if ((double)v < p.lo[j]) v = (float)p.lo[j];
@@ -97,7 +100,7 @@ __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen,
         v = (float)w;
       }
     }
-    trial[j] = v;
+    trial[j * tgs] = v;
   }
 }
 
@@ -106,7 +109,7 @@ __global__ void de_init_kernel(LigandsDev L, DEParams p, int g_stride, float *po
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)L.n_ligs * p.pop) return;
   const int lig = (int)(t / p.pop), i = (int)(t % p.pop);
-  init_individual(p, L.hdr[lig].n_tors, lig, i, g_stride, pop + t * g_stride);
+  init_individual(p, L.hdr[lig].n_tors, lig, i, g_stride, pop + t * g_stride, 1);
 }
 
 __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride, const float *pop, float *trials) {
@@ -114,48 +117,75 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
   if (t >= (int64_t)L.n_ligs * p.pop) return;
   const int lig = (int)(t / p.pop), i = (int)(t % p.pop);
   const float *base = pop + (int64_t)lig * p.pop * g_stride;
-  trial_individual(p, L.hdr[lig].n_tors, lig, gen, i, g_stride, base, trials + t * g_stride);
+  trial_individual(p, L.hdr[lig].n_tors, lig, gen, i, g_stride, base, g_stride, 1, trials + t * g_stride, 1);
 }
 
-// The whole search of one ligand, run by one workgroup (lane t handles
-// individuals t, t + blockDim.x, ...).
-template <int LAYOUT>
+// The whole search of one ligand, run by one workgroup.  The per-individual
+// steps without a pose (initial genotypes, DE trials, copies) use lane t for
+// individuals t, t + blockDim.x, ...; the scoring passes use LP lanes per
+// individual, the lanes of one individual in the two halves of a wavefront when
+// LP = 2.  The population is worked on in a gene-major copy W (gene j of
+// individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
+// touch neighbouring words; the caller's individual-major population is read
+// at the start and written back at the end.
+template <int LAYOUT, int LP>
 __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
+  constexpr int kStride = kWave / LP;   // individuals per wavefront in a scoring pass
   const int t = threadIdx.x, NT = blockDim.x;
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const int h = LP == 2 ? lane >> 5 : 0;            // which lane of the individual
+  const int sidx = wave * kStride + (lane & (kStride - 1));
+  const int SNT = NT / LP;
   const LigHeader H = S.L.hdr[lig];
   const int P = S.p.pop, G = S.g_stride;
   float *pop = S.population + (int64_t)lig * P * G;
   float *E = S.pop_energy + (int64_t)lig * P;
+  float *W = S.work + (int64_t)lig * P * G;
   float *T = S.trials + (int64_t)lig * P * G;
   const bool track = S.target != nullptr && S.gen_reached != nullptr;
   const float tgt = track ? S.target[lig] : 0.f;
+  auto score = [&](const float *g, int gs) {
+    return score_pose<kStride, LAYOUT, LP>(S.L, S.geom, S.ff, S.maps, H, g, gs, my);
+  };
+  for (int c = 0; c < P; c += NT) {
+    const int i = c + t;
+    if (i >= P) continue;
+    if (S.init) {
+      init_individual(S.p, H.n_tors, lig, i, G, W + i, P);
+    } else {
+      const float *row = pop + (int64_t)i * G;
+      for (int j = 0; j < G; ++j) W[j * P + i] = row[j];
+    }
+  }
+  __syncthreads();
   if (S.init) {
-    for (int c = 0; c < P; c += NT) {
-      const int i = c + t;
+    for (int c = 0; c < P; c += SNT) {
+      const int i = c + sidx;
       if (i < P) {
-        float *row = pop + (int64_t)i * G;
-        init_individual(S.p, H.n_tors, lig, i, G, row);
-        E[i] = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, row, my);
+        const float e = score(W + i, P);
+        E[i] = e;  // (both lanes of an individual store the same value)
       }
     }
   }
-  // a round of outside proposals (one per individual): exact score, greedy
-  // replacement -- skipped for a ligand that has already stopped at its target
+  // a round of outside proposals (individual-major, one per individual): exact
+  // score, greedy replacement -- skipped for a ligand that has already stopped
+  // at its target
   if (S.proposals && !(S.stop && !S.init && S.gen_reached && S.gen_reached[lig] >= 0)) {
     const float *Q = S.proposals + (int64_t)lig * P * G;
-    for (int c = 0; c < P; c += NT) {
-      const int i = c + t;
+    for (int c = 0; c < P; c += SNT) {
+      const int i = c + sidx;
       if (i < P) {
         const float *pr = Q + (int64_t)i * G;
-        const float e = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, pr, my);
+        const float e = score(pr, 1);
         if (e <= E[i]) {
-          float *row = pop + (int64_t)i * G;
-          for (int j = 0; j < G; ++j) row[j] = pr[j];
-          E[i] = e;
+          for (int j = h; j < G; j += LP) W[j * P + i] = pr[j];
+          E[i] = e;  // (both lanes of an individual store the same value)
         }
       }
     }
   }
+  // the energies just written come from the scoring lanes of each individual
+  __syncthreads();
   int reached = -1;
   if (track) {
     int hit = 0;
@@ -175,21 +205,19 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
     // every trial of the generation is drawn from the population as it stood
     for (int c = 0; c < P; c += NT) {
       const int i = c + t;
-      if (i < P) trial_individual(S.p, H.n_tors, lig, g, i, G, pop, T + (int64_t)i * G);
+      if (i < P) trial_individual(S.p, H.n_tors, lig, g, i, G, W, 1, P, T + i, P);
     }
     __syncthreads();
     int hit = 0;
-    for (int c = 0; c < P; c += NT) {
-      const int i = c + t;
+    for (int c = 0; c < P; c += SNT) {
+      const int i = c + sidx;
       if (i < P) {
-        const float *tr = T + (int64_t)i * G;
-        const float e = score_pose<kWave, LAYOUT>(S.L, S.geom, S.ff, S.maps, H, tr, my);
+        const float e = score(T + i, P);
         float ei = E[i];
         if (e <= ei) {
-          float *row = pop + (int64_t)i * G;
-          for (int j = 0; j < G; ++j) row[j] = tr[j];
-          E[i] = e;
+          for (int j = h; j < G; j += LP) W[j * P + i] = T[j * P + i];
           ei = e;
+          E[i] = e;  // (both lanes of an individual store the same value)
         }
         hit |= ei <= tgt;
       }
@@ -203,6 +231,14 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
     }
   }
   if (track && t == 0) S.gen_reached[lig] = reached;
+  // the population back in the caller's layout
+  for (int c = 0; c < P; c += NT) {
+    const int i = c + t;
+    if (i < P) {
+      float *row = pop + (int64_t)i * G;
+      for (int j = 0; j < G; ++j) row[j] = W[j * P + i];
+    }
+  }
   // best member: first index of the smallest energy
   __shared__ int s_best;
   if (t == 0) {
@@ -214,26 +250,27 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   }
   __syncthreads();
   const int bi = s_best;
-  for (int j = t; j < G; j += NT) S.best_g[(int64_t)lig * G + j] = pop[(int64_t)bi * G + j];
+  for (int j = t; j < G; j += NT) S.best_g[(int64_t)lig * G + j] = W[(int64_t)j * P + bi];
   __syncthreads();
 }
 
 // Persistent: each workgroup keeps taking ligands from the queue until none is
-// left.  Wavefront w of the group keeps its lanes' coordinates in its own LDS
-// region of lds_atoms * 3 rows of 64 dwords.
-template <int LAYOUT>
+// left.  Wavefront w of the group keeps its poses' coordinates in its own LDS
+// region of lds_atoms * 3 rows of 64 / LP dwords.
+template <int LAYOUT, int LP>
 __global__ __launch_bounds__(kSearchMaxThreads, 2) void search_kernel(SearchLaunch S) {
+  constexpr int kStride = kWave / LP;
   extern __shared__ float lds[];
   __shared__ int s_q;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  float *my = lds + (size_t)wave * 3 * S.lds_atoms * kWave + lane;
+  float *my = lds + (size_t)wave * 3 * S.lds_atoms * kStride + (lane & (kStride - 1));
   for (;;) {
     if (threadIdx.x == 0) s_q = atomicAdd(S.queue, 1);
     __syncthreads();
     const int q = s_q;
     __syncthreads();
     if (q >= S.n_order) break;
-    search_ligand<LAYOUT>(S, S.order[q], my);
+    search_ligand<LAYOUT, LP>(S, S.order[q], my);
   }
 }
 
@@ -262,56 +299,96 @@ hipError_t launch_fill_i32(int32_t *p, int32_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int LAYOUT>
-static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, hipStream_t s, const char **step) {
-  // Wavefronts per workgroup, w: up to one per 64 individuals.  Each wavefront's
-  // LDS region is sized for the bucket's largest ligand, so a larger w can leave
-  // fewer wavefronts resident per CU.  Pick the w that minimises (rounds of
-  // resident ligands) x (64-individual chunks per ligand per generation).
-  const size_t per_wave = (size_t)S.lds_atoms * 3 * kWave * sizeof(float);
-  const int want = std::min((S.p.pop + kWave - 1) / kWave, kSearchMaxThreads / kWave);
+template <int LAYOUT, int LP>
+static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t waves, hipStream_t s,
+                                  const char **step) {
+  // Wavefronts per workgroup, w: up to one per 64 / LP individuals.  Each
+  // wavefront's LDS region is sized for the bucket's largest ligand, so a larger
+  // w can leave fewer wavefronts resident per CU.  Unless the caller fixes w,
+  // pick the w that minimises (rounds of resident ligands) x (scoring passes per
+  // generation).
+  auto kernel = (const void *)search_kernel<LAYOUT, LP>;
+  const int per_pass = kWave / LP;
+  const size_t per_wave = (size_t)S.lds_atoms * 3 * per_pass * sizeof(float);
+  const int want = std::min((S.p.pop + per_pass - 1) / per_pass, kSearchMaxThreads / kWave);
   // The dynamic LDS allowance is what the CU holds less the kernel's static LDS
   // (its __shared__ variables plus what the compiler adds for block reductions).
   hipFuncAttributes fa;
   *step = "hipFuncGetAttributes";
-  if (hipError_t e = hipFuncGetAttributes(&fa, (const void *)search_kernel<LAYOUT>); e != hipSuccess) return e;
+  if (hipError_t e = hipFuncGetAttributes(&fa, kernel); e != hipSuccess) return e;
   if (fa.sharedSizeBytes >= kLdsPerCU) return hipErrorInvalidConfiguration;
   const size_t max_dyn = kLdsPerCU - fa.sharedSizeBytes;
+  const int max_w = std::max(want, std::min(waves, kSearchMaxThreads / kWave));
   *step = "hipFuncSetAttribute (largest size)";
-  if (per_wave > 65536 || per_wave * want > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)search_kernel<LAYOUT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)std::min<size_t>(max_dyn, per_wave * want));
+  if (per_wave * max_w > 65536) {
+    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)std::min<size_t>(max_dyn, per_wave * max_w));
     if (e != hipSuccess) return e;
   }
-  int best_w = 1, best_blocks = 0;
-  int64_t best_cost = -1;
-  for (int w = 1; w <= want; ++w) {
-    if (per_wave * w > max_dyn) break;
-    int blocks = 0;
+  // Resident workgroups per CU: bounded by the CU's LDS (dynamic + static per
+  // workgroup) and by its vector registers (512 per lane per SIMD, allocated in
+  // steps of 8, at most 8 wavefronts per SIMD).  The runtime's occupancy query
+  // is also taken, and the larger answer used: a workgroup that does not fit
+  // waits for a free slot, which a persistent kernel with a work queue tolerates.
+  const int vgprs = std::max(8, (fa.numRegs + 7) / 8 * 8);
+  const int waves_per_cu = 4 * std::min(8, 512 / vgprs);
+  auto resident = [&](int w, int *blocks) -> hipError_t {
+    *blocks = 0;
+    if (per_wave * w > max_dyn) return hipSuccess;
     *step = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)search_kernel<LAYOUT>,
-                                                                w * kWave, per_wave * w);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, kernel, w * kWave, per_wave * w);
     if (e != hipSuccess) return e;
-    if (blocks < 1) continue;
-    const int64_t slots = (int64_t)n_cu * blocks;
-    const int64_t rounds = (S.n_order + slots - 1) / slots;
-    const int64_t chunks = (S.p.pop + w * kWave - 1) / (w * kWave);
-    if (best_cost < 0 || rounds * chunks < best_cost) best_cost = rounds * chunks, best_w = w, best_blocks = blocks;
+    const int by_lds = (int)(kLdsPerCU / (per_wave * w + fa.sharedSizeBytes));
+    *blocks = std::max(*blocks, std::min(by_lds, waves_per_cu / w));
+    return hipSuccess;
+  };
+  int best_w = 0, best_blocks = 0;
+  if (waves > 0) {
+    // the caller's count, lowered to what the LDS of one CU holds
+    for (best_w = std::min(waves, kSearchMaxThreads / kWave); best_w > 1 && per_wave * best_w > max_dyn; --best_w) {
+    }
+    if (hipError_t e = resident(best_w, &best_blocks); e != hipSuccess) return e;
+    if (best_blocks < 1) return hipErrorInvalidConfiguration;
+  } else {
+    int64_t best_cost = -1;
+    for (int w = 1; w <= want; ++w) {
+      int blocks = 0;
+      if (hipError_t e = resident(w, &blocks); e != hipSuccess) return e;
+      if (blocks < 1) continue;
+      const int64_t slots = (int64_t)n_cu * blocks;
+      const int64_t rounds = (S.n_order + slots - 1) / slots;
+      const int64_t passes = (S.p.pop + w * per_pass - 1) / (w * per_pass);
+      if (best_cost < 0 || rounds * passes < best_cost) best_cost = rounds * passes, best_w = w, best_blocks = blocks;
+    }
+    if (best_w == 0) return hipErrorInvalidConfiguration;
   }
   const size_t lds = per_wave * best_w;
-  const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * std::max(best_blocks, 1));
+  const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * best_blocks);
   *step = "search kernel launch";
-  hipLaunchKernelGGL(search_kernel<LAYOUT>, dim3((unsigned)grid), dim3(best_w * kWave), lds, s, S);
+  void (*const fn)(SearchLaunch) = search_kernel<LAYOUT, LP>;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(best_w * kWave), lds, s, S);
   return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, hipStream_t s, const char **step) {
+template <int LAYOUT>
+static hipError_t launch_search_lp(const SearchLaunch &S, int32_t n_cu, SearchShape shape, hipStream_t s,
+                                   const char **step) {
+  if (shape.lanes_per_pose == 2) return launch_search_t<LAYOUT, 2>(S, n_cu, shape.waves, s, step);
+  return launch_search_t<LAYOUT, 1>(S, n_cu, shape.waves, s, step);
+}
+
+bool search_shape_fits(int32_t lds_atoms, SearchShape shape) {
+  const size_t per_wave = (size_t)lds_atoms * 3 * (kWave / shape.lanes_per_pose) * sizeof(float);
+  return per_wave * (size_t)std::max(shape.waves, 1) + 1024 <= kLdsPerCU;
+}
+
+hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, SearchShape shape, hipStream_t s,
+                         const char **step) {
   if (S.n_order <= 0) return hipSuccess;
   switch (layout) {
-    case kLinear: return launch_search_t<kLinear>(S, n_cu, s, step);
-    case kZPair: return launch_search_t<kZPair>(S, n_cu, s, step);
-    case kYZQuad: return launch_search_t<kYZQuad>(S, n_cu, s, step);
+    case kLinear: return launch_search_lp<kLinear>(S, n_cu, shape, s, step);
+    case kZPair: return launch_search_lp<kZPair>(S, n_cu, shape, s, step);
+    case kYZQuad: return launch_search_lp<kYZQuad>(S, n_cu, shape, s, step);
   }
   return hipErrorInvalidValue;
 }

@@ -81,6 +81,9 @@ _SIGS = {
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
     "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
+    "dock_search_shapes": [_P, _P],
+    "dock_search_set_shapes": [_P, _P],
+    "dock_search_autotune": [_P, _P, _P, C.c_int32, C.c_int32, _P],
     "dock_mlp_create": [C.c_int32, C.c_uint64, _P],
     "dock_mlp_destroy": [_P],
     "dock_mlp_set_params": [_P, _P],
@@ -311,6 +314,33 @@ def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):
     """Pair terms alone on register coordinates (roofline probe)."""
     _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane, _dptr(out, "float32", "out"),
                                 _stream(stream)))
+
+
+# ---------------------------------------------------------------- search launch shapes
+DOCK_SEARCH_BUCKETS = 5
+
+
+class _Shape(C.Structure):
+    _fields_ = [("max_atoms", C.c_int32), ("lanes_per_pose", C.c_int32), ("waves_per_group", C.c_int32)]
+
+
+def dock_search_shapes(ligs: Ligands):
+    """[(max_atoms, lanes_per_pose, waves_per_group)] per ligand-size bucket."""
+    arr = (_Shape * DOCK_SEARCH_BUCKETS)()
+    _check(_lib.dock_search_shapes(ligs.handle, arr))
+    return [(a.max_atoms, a.lanes_per_pose, a.waves_per_group) for a in arr]
+
+
+def dock_search_set_shapes(ligs: Ligands, shapes):
+    arr = (_Shape * DOCK_SEARCH_BUCKETS)(*[_Shape(*x) for x in shapes])
+    _check(_lib.dock_search_set_shapes(ligs.handle, arr))
+
+
+def dock_search_autotune(pocket: Pocket, ligs: Ligands, params: SearchParams, g_stride: int,
+                         tune_generations: int = 3, stream=None):
+    P = params._c()
+    _check(_lib.dock_search_autotune(pocket.handle, ligs.handle, C.byref(P), g_stride, tune_generations,
+                                     _stream(stream)))
 
 
 # ---------------------------------------------------------------- learned proposal

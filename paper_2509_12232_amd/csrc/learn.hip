@@ -121,13 +121,15 @@ __global__ void reduce_partial_kernel(const float *partial, int chunks, int n, f
   out[i] = s;
 }
 
-// partial[chunk][c] = sum over the rows m of the chunk of Z[m][c] (row order);
-// neighbouring threads read neighbouring columns of a row
+// partial[chunk][c] = sum over the rows m of the chunk (kColsumChunk rows) of
+// Z[m][c] (row order); neighbouring threads read neighbouring columns of a row
+constexpr int kColsumChunk = 64;
+
 __global__ void colsum_partial_kernel(const bf16 *Z, int64_t mp, int N, float *partial) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  const int64_t m0 = (int64_t)blockIdx.y * kWgradChunk;
-  const int64_t m1 = m0 + kWgradChunk < mp ? m0 + kWgradChunk : mp;
+  const int64_t m0 = (int64_t)blockIdx.y * kColsumChunk;
+  const int64_t m1 = m0 + kColsumChunk < mp ? m0 + kColsumChunk : mp;
   float s = 0.f;
   for (int64_t m = m0; m < m1; ++m) s += (float)Z[m * N + c];
   partial[(int64_t)blockIdx.y * N + c] = s;
@@ -188,11 +190,20 @@ __global__ __launch_bounds__(256) void mlp_loss_kernel(const float *y, const flo
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void ordered_sum_kernel(const float *part, int n, float scale, float *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[0] = scale * sum of part[0 .. n): one block of 256 threads, thread t
+// summing part[t], part[t + 256], ... in order, then a fixed tree -- the same
+// order on every call
+__global__ __launch_bounds__(256) void ordered_sum_kernel(const float *part, int n, float scale, float *out) {
+  __shared__ float sh[256];
   float s = 0.f;
-  for (int i = 0; i < n; ++i) s += part[i];
-  out[0] = s * scale;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0] * scale;
 }
 
 // bfloat16 copies of weight element e of the packed vector (e < kOffW3 + 256 * 32,
@@ -470,10 +481,12 @@ static hipError_t wgrad(const bf16 *Xp8, const bf16 *Zp8, int64_t mp, int K, int
   return hipGetLastError();
 }
 
-// out[c] = column sums of Z, by chunks of kWgradChunk rows summed in chunk order
-// (partial needs ceil(mp / kWgradChunk) * N floats)
+// out[c] = column sums of Z, by chunks of kColsumChunk rows summed in chunk
+// order (partial needs ceil(mp / kColsumChunk) * N floats, which the weight
+// gradients' ceil(mp / kWgradChunk) * 256 * 256 always cover)
 static hipError_t colsum(const bf16 *Z, int64_t mp, int N, float *partial, float *out, hipStream_t s) {
-  const int chunks = (int)((mp + kWgradChunk - 1) / kWgradChunk);
+  static_assert(kWgradChunk / kColsumChunk * kMlpHidden <= kMlpHidden * kMlpHidden, "partial buffer size");
+  const int chunks = (int)((mp + kColsumChunk - 1) / kColsumChunk);
   hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks_for(N, 64), chunks), dim3(64), 0, s, Z, mp, N, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -519,7 +532,7 @@ hipError_t launch_mlp_backward(const MlpWeights &W, const MlpActs &A, const MlpG
                      (float)(2.0 / (double)m), G.g3, G.g3p8, G.loss_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(64), 0, s, (const float *)G.loss_part, (int)lb,
+  hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, s, (const float *)G.loss_part, (int)lb,
                      (float)(1.0 / (double)m), G.loss);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // layer 3

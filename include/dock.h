@@ -228,6 +228,24 @@ dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, con
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);
 
+/* ---- Search plans: one captured graph per search -------------------------------
+ * A plan holds its own scratch (trials and the gene-major population copy,
+ * 2 x n_ligands x pop_size x g_stride floats, and the bucket queues) and the
+ * whole search -- every bucket's persistent launch on the side streams, the
+ * proposal rounds of a learned search, the joins -- captured once into a HIP
+ * graph.  Launching it enqueues the same search as dock_search with the
+ * arguments given at creation (the same pointers; their contents are read at
+ * launch time), as one graph launch, with no allocation.  The launch shapes
+ * in force at creation are the ones captured.  Launches of one plan must not
+ * overlap (they share its scratch).  Errors as dock_search. */
+typedef struct dock_search_plan dock_search_plan;
+dock_status dock_search_plan_create(const dock_pocket *pocket, const dock_ligands *ligs,
+                                    const dock_search_params *params, int32_t g_stride, float *population,
+                                    float *pop_energy, float *best_genotypes, float *best_energies,
+                                    const float *target, int32_t *gen_reached, dock_search_plan **out);
+dock_status dock_search_plan_launch(dock_search_plan *plan, void *stream);
+dock_status dock_search_plan_destroy(dock_search_plan *plan);
+
 /* ---- Launch shapes of the search and their autotuner --------------------------
  * dock_search runs one persistent kernel per ligand-size bucket (atom counts
  * up to 16, 32, 48, 64, 96).  Its shape: lanes per pose (1: each lane builds

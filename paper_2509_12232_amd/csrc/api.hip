@@ -727,9 +727,10 @@ static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, Searc
   return e;
 }
 
-extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
-                                   int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
-                                   float *best_energies, const float *target, int32_t *gen_reached, void *stream) {
+static dock_status check_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                int32_t g_stride, const float *population, const float *pop_energy,
+                                const float *best_genotypes, const float *best_energies, const float *target,
+                                const int32_t *gen_reached) {
   dock_status st = check_pair(p, L);
   if (st) return st;
   if ((st = check_params(q))) return st;
@@ -737,8 +738,8 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
     return set_err(DOCK_E_INVALID, "null output buffer");
   if (g_stride < 7 + L->max_tors) return set_err(DOCK_E_INVALID, "g_stride too small");
   if ((int64_t)q->first_generation + q->n_generations > 0x7fffffff) return set_err(DOCK_E_INVALID, "too many generations");
-  const bool track = target && gen_reached;
-  if (q->stop_at_target && !track) return set_err(DOCK_E_INVALID, "stop_at_target needs target and gen_reached");
+  if (q->stop_at_target && !(target && gen_reached))
+    return set_err(DOCK_E_INVALID, "stop_at_target needs target and gen_reached");
   const dock_mlp *net = q->proposal;
   if (net) {
     if (mlp_device(net) != p->device) return set_err(DOCK_E_INVALID, "proposal network on another device");
@@ -746,11 +747,24 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
       return set_err(DOCK_E_INVALID, "proposal_step must be positive and finite");
     if (q->proposal_every < 0) return set_err(DOCK_E_INVALID, "proposal_every must be >= 0");
   }
-  DeviceScope ds(p->device);
-  HIP_TRY(ds.err, "hipSetDevice");
-  hipStream_t s = (hipStream_t)stream;
-  const int nl = L->n_ligs, P = q->pop_size;
-  const int64_t n = (int64_t)nl * P;
+  return DOCK_OK;
+}
+
+// Scratch of one search: trials and the gene-major population, [n_ligs][g_stride][pop]
+// each, and one queue counter per bucket.
+struct SearchScratch {
+  float *trials = nullptr, *work = nullptr;
+  int32_t *queues = nullptr;
+};
+
+// Enqueues a whole search (validated arguments, scratch in place) on s.
+static hipError_t enqueue_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                 int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
+                                 float *best_energies, const float *target, int32_t *gen_reached,
+                                 const SearchScratch &X, hipStream_t s, const char **step) {
+  const bool track = target && gen_reached;
+  const dock_mlp *net = q->proposal;
+  const int P = q->pop_size;
   SearchLaunch S{};
   S.L = L->view();
   S.geom = p->geom;
@@ -766,63 +780,156 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   S.target = track ? target : nullptr;
   S.gen_reached = track ? gen_reached : nullptr;
   S.stop = q->stop_at_target ? 1 : 0;
-  int32_t *queues = nullptr;
-  const char *step = "search buffers";
-  hipError_t e = hipMallocAsync((void **)&S.trials, sizeof(float) * n * g_stride, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&S.work, sizeof(float) * n * g_stride, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&queues, sizeof(int32_t) * L->buckets.size(), s);
-  if (e == hipSuccess && !net) {
-    e = search_pass(p, L, S, queues, s, &step);
-  } else if (e == hipSuccess) {
-    // Learned proposals: a round fills the trial buffer with one proposal per
-    // individual; the next persistent pass scores them and takes each greedily
-    // before its generations (the pass's DE trials reuse that buffer afterwards).
-    const PopRows R = make_pop_rows(L, P, g_stride, q->box_lo, q->box_hi);
-    const int g0 = q->first_generation, g_end = g0 + q->n_generations;
-    const int every = q->proposal_every;
-    auto propose = [&](int gen) {
-      step = "proposals";
-      return run_proposals(net, R, q->proposal_step, q->seed, gen, population, S.trials, s);
-    };
-    bool pending = false;
-    if (q->init) {
-      // the initial population and its scores, then the first round
-      SearchLaunch T = S;
-      T.p.n_gen = 0;
-      e = search_pass(p, L, T, queues, s, &step);
-      if (e == hipSuccess) e = propose(g0);
-      pending = true;
-    } else if (every > 0 && g0 > 0 && g0 % every == 0 && g0 < q->proposal_until && g0 < g_end) {
-      // later rounds come before the generations g > 0 that are multiples of
-      // proposal_every (g < proposal_until), so a search split into resumed
-      // calls runs the same rounds as one call
-      e = propose(g0);
-      pending = true;
+  S.trials = X.trials;
+  S.work = X.work;
+  if (!net) return search_pass(p, L, S, X.queues, s, step);
+  // Learned proposals: a round fills the trial buffer with one proposal per
+  // individual; the next persistent pass scores them and takes each greedily
+  // before its generations (the pass's DE trials reuse that buffer afterwards).
+  const PopRows R = make_pop_rows(L, P, g_stride, q->box_lo, q->box_hi);
+  const int g0 = q->first_generation, g_end = g0 + q->n_generations;
+  const int every = q->proposal_every;
+  auto propose = [&](int gen) {
+    *step = "proposals";
+    return run_proposals(net, R, q->proposal_step, q->seed, gen, population, S.trials, s);
+  };
+  hipError_t e = hipSuccess;
+  bool pending = false;
+  if (q->init) {
+    // the initial population and its scores, then the first round
+    SearchLaunch T = S;
+    T.p.n_gen = 0;
+    e = search_pass(p, L, T, X.queues, s, step);
+    if (e == hipSuccess) e = propose(g0);
+    pending = true;
+  } else if (every > 0 && g0 > 0 && g0 % every == 0 && g0 < q->proposal_until && g0 < g_end) {
+    // later rounds come before the generations g > 0 that are multiples of
+    // proposal_every (g < proposal_until), so a search split into resumed
+    // calls runs the same rounds as one call
+    e = propose(g0);
+    pending = true;
+  }
+  int g = g0;
+  while (e == hipSuccess) {
+    int seg_end = g_end;
+    if (every > 0) {
+      const int64_t nb = ((int64_t)g / every + 1) * every;
+      if (nb < q->proposal_until && nb < g_end) seg_end = (int)nb;
     }
-    int g = g0;
-    while (e == hipSuccess) {
-      int seg_end = g_end;
-      if (every > 0) {
-        const int64_t nb = ((int64_t)g / every + 1) * every;
-        if (nb < q->proposal_until && nb < g_end) seg_end = (int)nb;
-      }
-      SearchLaunch T = S;
-      T.init = 0;
-      T.p.first_gen = g;
-      T.p.n_gen = seg_end - g;
-      T.proposals = pending ? S.trials : nullptr;
-      e = search_pass(p, L, T, queues, s, &step);
-      pending = false;
-      g = seg_end;
-      if (g >= g_end) break;
-      if (e == hipSuccess) e = propose(g);
-      pending = true;
+    SearchLaunch T = S;
+    T.init = 0;
+    T.p.first_gen = g;
+    T.p.n_gen = seg_end - g;
+    T.proposals = pending ? S.trials : nullptr;
+    e = search_pass(p, L, T, X.queues, s, step);
+    pending = false;
+    g = seg_end;
+    if (g >= g_end) break;
+    if (e == hipSuccess) e = propose(g);
+    pending = true;
+  }
+  return e;
+}
+
+extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                   int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
+                                   float *best_energies, const float *target, int32_t *gen_reached, void *stream) {
+  dock_status st = check_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target,
+                                gen_reached);
+  if (st) return st;
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nf = (size_t)L->n_ligs * q->pop_size * g_stride;
+  SearchScratch X;
+  const char *step = "search buffers";
+  hipError_t e = hipMallocAsync((void **)&X.trials, sizeof(float) * nf, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&X.work, sizeof(float) * nf, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&X.queues, sizeof(int32_t) * L->buckets.size(), s);
+  if (e == hipSuccess)
+    e = enqueue_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target, gen_reached,
+                       X, s, &step);
+  if (X.queues) (void)hipFreeAsync(X.queues, s);
+  if (X.work) (void)hipFreeAsync(X.work, s);
+  if (X.trials) (void)hipFreeAsync(X.trials, s);
+  if (e != hipSuccess) return hip_err(e, step);
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ search plans
+struct dock_search_plan {
+  int device = 0;
+  SearchScratch X;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void free_plan(dock_search_plan *P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (void *b : {(void *)P->X.trials, (void *)P->X.work, (void *)P->X.queues})
+    if (b) (void)hipFree(b);
+  delete P;
+}
+
+extern "C" dock_status dock_search_plan_create(const dock_pocket *p, const dock_ligands *L,
+                                               const dock_search_params *q, int32_t g_stride, float *population,
+                                               float *pop_energy, float *best_genotypes, float *best_energies,
+                                               const float *target, int32_t *gen_reached, dock_search_plan **out) {
+  if (!out) return set_err(DOCK_E_INVALID, "null out");
+  *out = nullptr;
+  dock_status st = check_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target,
+                                gen_reached);
+  if (st) return st;
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  dock_search_plan *P = new dock_search_plan();
+  P->device = p->device;
+  const size_t nf = (size_t)L->n_ligs * q->pop_size * g_stride;
+  const char *step = "plan buffers";
+  hipError_t e = hipMalloc((void **)&P->X.trials, sizeof(float) * nf);
+  if (e == hipSuccess) e = hipMalloc((void **)&P->X.work, sizeof(float) * nf);
+  if (e == hipSuccess) e = hipMalloc((void **)&P->X.queues, sizeof(int32_t) * L->buckets.size());
+  // capture on a private stream (default priority); the side streams join the
+  // capture through the fork/join events
+  hipStream_t cs = nullptr;
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> guard(L->side_mu);
+    e = L->ensure_side_streams();  // created before the capture starts
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    step = "graph capture";
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      hipError_t w = enqueue_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target,
+                                    gen_reached, P->X, cs, &step);
+      hipError_t c = hipStreamEndCapture(cs, &P->graph);
+      e = w != hipSuccess ? w : c;
     }
   }
-  if (queues) (void)hipFreeAsync(queues, s);
-  if (S.work) (void)hipFreeAsync(S.work, s);
-  if (S.trials) (void)hipFreeAsync(S.trials, s);
-  if (e != hipSuccess) return hip_err(e, step);
+  if (e == hipSuccess) step = "graph instantiate", e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    free_plan(P);
+    return hip_err(e, step);
+  }
+  *out = P;
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search_plan_launch(dock_search_plan *P, void *stream) {
+  if (!P) return set_err(DOCK_E_INVALID, "null plan");
+  DeviceScope ds(P->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(hipGraphLaunch(P->exec, (hipStream_t)stream), "graph launch");
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search_plan_destroy(dock_search_plan *P) {
+  if (!P) return DOCK_OK;
+  DeviceScope ds(P->device);
+  free_plan(P);
   return DOCK_OK;
 }
 

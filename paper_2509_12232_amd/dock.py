@@ -81,6 +81,9 @@ _SIGS = {
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
     "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
+    "dock_search_plan_create": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
+    "dock_search_plan_launch": [_P, _P],
+    "dock_search_plan_destroy": [_P],
     "dock_search_shapes": [_P, _P],
     "dock_search_set_shapes": [_P, _P],
     "dock_search_autotune": [_P, _P, _P, C.c_int32, C.c_int32, _P],
@@ -314,6 +317,41 @@ def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):
     """Pair terms alone on register coordinates (roofline probe)."""
     _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane, _dptr(out, "float32", "out"),
                                 _stream(stream)))
+
+
+# ---------------------------------------------------------------- search plans
+class SearchPlan:
+    """Owner of a dock_search_plan (a search captured into one HIP graph).  Keeps
+    the buffers it was created with alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+        self._destroy = _lib.dock_search_plan_destroy
+
+    def __del__(self):
+        if getattr(self, "handle", None) and getattr(self, "_destroy", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+
+def dock_search_plan_create(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy,
+                            best_genotypes, best_energies, target=None, gen_reached=None) -> SearchPlan:
+    P = params._c()
+    out = C.c_void_p()
+    _check(_lib.dock_search_plan_create(pocket.handle, ligs.handle, C.byref(P), int(population.shape[-1]),
+                                        _dptr(population, "float32", "population"),
+                                        _dptr(pop_energy, "float32", "pop_energy"),
+                                        _dptr(best_genotypes, "float32", "best_genotypes"),
+                                        _dptr(best_energies, "float32", "best_energies"),
+                                        _dptr(target, "float32", "target"),
+                                        _dptr(gen_reached, "int32", "gen_reached"), C.byref(out)))
+    return SearchPlan(out, (pocket, ligs, params.proposal, population, pop_energy, best_genotypes, best_energies,
+                            target, gen_reached))
+
+
+def dock_search_plan_launch(plan: SearchPlan, stream=None):
+    _check(_lib.dock_search_plan_launch(plan.handle, _stream(stream)))
 
 
 # ---------------------------------------------------------------- search launch shapes

@@ -37,7 +37,7 @@ def test_binding_names_match_abi():
     from paper_2509_12232_amd import dock
     for n in declared_entry_points():
         if n in ("dock_last_error", "dock_destroy_pocket", "dock_destroy_ligands", "dock_ligand_pair_count",
-                 "dock_pocket_layout", "dock_mlp_destroy"):
+                 "dock_pocket_layout", "dock_mlp_destroy", "dock_search_plan_destroy"):
             continue
         assert hasattr(dock, n), n
 

@@ -209,3 +209,54 @@ def test_launch_shape_does_not_change_results(dk):
     np.testing.assert_array_equal(reached[0][1], reached[1][1])
     assert np.all((reached[0][0] >= 0) & (reached[0][0] <= 6))
     assert np.all(reached[0][1] <= ref[3] + 0.1)
+
+
+def test_search_plan_graph_replays(dk):
+    """A search captured into a HIP graph gives, on every replay (with eager work
+    and synchronisations between the replays), exactly dock_search's result --
+    plain, learned, and stopping at targets."""
+    import torch
+    ff, rec, grid, maps = system(2, grid_n=48)
+    atoms = [12, 20, 31, 40, 52, 70, 90]
+    ligands = [synth.make_ligand(1, 500 + i, n, min(10, n // 4), 8) for i, n in enumerate(atoms)]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    nl = len(ligands)
+    net = dk.dock_mlp_create(0, 5)
+    cases = [dict(), dict(proposal=net, proposal_step=0.5, proposal_every=2, proposal_until=5)]
+    for kw in cases:
+        params = _params(dk, lo, hi, pop_size=75, n_generations=6, **kw)
+        ref = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, nl, stride)[:4]]
+        buf = [torch.zeros((nl, 75, stride), dtype=torch.float32, device="cuda"),
+               torch.zeros((nl, 75), dtype=torch.float32, device="cuda"),
+               torch.zeros((nl, stride), dtype=torch.float32, device="cuda"),
+               torch.zeros(nl, dtype=torch.float32, device="cuda")]
+        plan = dk.dock_search_plan_create(pocket, ligs, params, *buf)
+        for rep in range(3):
+            for b in buf:
+                b.fill_(7.0)                       # eager work between replays
+            dk.dock_search_plan_launch(plan)
+            torch.cuda.synchronize()
+            for x, y in zip(ref, buf):
+                assert np.array_equal(x.view(np.uint32), y.cpu().numpy().view(np.uint32)), (kw.keys(), rep)
+            _run_gpu_search(dk, pocket, ligs, params, nl, stride)   # an eager search in between
+        del plan
+    # stopping at targets
+    params = _params(dk, lo, hi, pop_size=75, n_generations=6, stop_at_target=1)
+    target = torch.from_numpy(ref[3] + 0.5).cuda()
+    r = _run_gpu_search(dk, pocket, ligs, params, nl, stride, target=target)
+    want = [x.cpu().numpy() for x in r[:4]] + [r[4].cpu().numpy()]
+    buf = [torch.zeros((nl, 75, stride), dtype=torch.float32, device="cuda"),
+           torch.zeros((nl, 75), dtype=torch.float32, device="cuda"),
+           torch.zeros((nl, stride), dtype=torch.float32, device="cuda"),
+           torch.zeros(nl, dtype=torch.float32, device="cuda"), target,
+           torch.full((nl,), -5, dtype=torch.int32, device="cuda")]
+    plan = dk.dock_search_plan_create(pocket, ligs, params, *buf)
+    for rep in range(2):
+        buf[5].fill_(-5)
+        dk.dock_search_plan_launch(plan)
+        torch.cuda.synchronize()
+        for x, y in zip(want, buf[:4] + buf[5:]):
+            assert np.array_equal(x.view(np.uint32), y.cpu().numpy().view(np.uint32)), rep

@@ -154,7 +154,34 @@ def cpu_baseline(S, target_seconds: float, max_poses: int):
             break
         n = min(max_poses, int(n * max(2.0, 1.2 * target_seconds / max(t, 1e-3))))
     return {"value": n / t, "unit": "poses/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the 1e7 genotypes, scored in {t:.1f} s (FP64, {threads} threads)"}
+            "sample": f"first {n} of the 1e7 genotypes, scored in {t:.1f} s (FP64, {threads} threads)",
+            "search": cpu_search_baseline(threads)}
+
+
+def cpu_search_baseline(threads: int):
+    """The FP64 oracle's plain search (threads over ligands) on the single-ligand
+    workload (pop 64 x 100 generations) and on the first 20 ligands of the
+    1000-ligand batch (pop 128 x 200): poses scored per second."""
+    import oracle
+    out = {}
+    for cid, count in ((0, 1), (2, 20)):
+        c = synth.CONFIGS[cid]
+        nt = c["n_types"]
+        ff = synth.forcefield(nt)
+        grid = synth.make_grid(c["grid_n"], nt)
+        maps = oracle.build_maps(ff, synth.make_receptor(1, 2000, nt), grid, n_threads=threads)
+        ligands = synth.config_ligands(cid, count=count)
+        lo, hi = synth.pocket_box(grid)
+        stride = 7 + max(lg.n_torsions for lg in ligands)
+        p = oracle.SearchParams(pop_size=c["pop"], n_generations=c["gens"], seed=1, box_lo=tuple(lo),
+                                box_hi=tuple(hi))
+        t0 = time.perf_counter()
+        r = oracle.search(grid, maps, ff, ligands, p, stride, n_threads=threads)
+        dt = time.perf_counter() - t0
+        n = count * c["pop"] * (c["gens"] + 1)
+        out[f"{count}_ligands"] = {"poses_per_s": round(n / dt, 1), "seconds": round(dt, 2),
+                                   "best_median": round(float(np.median(r["best_energy"])), 4)}
+    return out
 
 
 def batch_setup(cfg_id: int, extra_cfg: int | None = None):
@@ -195,8 +222,18 @@ def search_throughput(B, gens: int, pop: int):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n = L.n * pop * (gens + 1)
+    # the same search captured once into a HIP graph and launched as one graph
+    plan = dk.dock_search_plan_create(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
+    dk.dock_search_plan_launch(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dk.dock_search_plan_launch(plan)
+    torch.cuda.synchronize()
+    graph_dt = time.perf_counter() - t0
+    del plan
     shapes = {f"<={b}": {"lanes_per_pose": lp, "waves": w} for b, lp, w in dk.dock_search_shapes(L)}
     return {"ligands": L.n, "pop": pop, "generations": gens, "seconds": round(dt, 4),
+            "graph_seconds": round(graph_dt, 4), "graph_poses_per_s": round(n / graph_dt, 1),
             "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4),
             "autotune_s": round(tune_s, 2), "shapes": shapes}
 

@@ -249,17 +249,18 @@ dock_status dock_search_plan_destroy(dock_search_plan *plan);
 /* ---- Launch shapes of the search and their autotuner --------------------------
  * dock_search runs one persistent kernel per ligand-size bucket (atom counts
  * up to 16, 32, 48, 64, 96).  Its shape: lanes per pose (1: each lane builds
- * and scores a pose; 2: two lanes share a pose, splitting its atoms and pair
- * records, which halves the LDS per wavefront) and wavefronts per workgroup (1-4,
- * 0 = chosen at launch from the ligand count and the LDS residency).  Energies,
- * and hence search results, do not depend on the shape: both forms sum the
+ * and scores a pose; 2 or 4: that many lanes share a pose, splitting its atoms
+ * and pair records, which divides the LDS per wavefront by as much) and
+ * wavefronts per workgroup (1-4, 0 = chosen at launch from the ligand count and
+ * the LDS residency).  Energies, and hence search results, do not depend on
+ * the shape: every form sums the
  * same partial sums in the same order.  Shapes are launch configuration kept in
  * the ligand handle (the one exception to its immutability): set or tune them
  * while no search on the handle is in flight. */
 #define DOCK_SEARCH_BUCKETS 5
 typedef struct {
   int32_t max_atoms;        /* the bucket's upper atom count (read-only: 16, 32, 48, 64, 96) */
-  int32_t lanes_per_pose;   /* 1 or 2 */
+  int32_t lanes_per_pose;   /* 1, 2 or 4 */
   int32_t waves_per_group;  /* 0..4 */
 } dock_search_shape;
 
@@ -269,7 +270,7 @@ dock_status dock_search_shapes(const dock_ligands *ligs, dock_search_shape *shap
 dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *shapes);
 /* Autotuner: for every non-empty bucket, times a search of tune_generations
  * generations (params' pop_size, seed, box) of the bucket's ligands for every
- * shape (1 and 2 lanes per pose x 1 up to 4 wavefronts), warm-up run first,
+ * shape (1, 2 and 4 lanes per pose x 1 up to 4 wavefronts), warm-up run first,
  * with HIP events on stream, and fixes the fastest.  Results are cached for the
  * process under (device, map layout and dimensions, bucket, its largest ligand,
  * pop_size); a cached bucket is not timed again, and dock_search uses cached

@@ -946,7 +946,8 @@ extern "C" dock_status dock_search_set_shapes(dock_ligands *L, const dock_search
   for (size_t b = 0; b < L->buckets.size(); ++b) {
     const dock_search_shape &x = shapes[b];
     if (x.max_atoms != L->buckets[b].upper) return set_err(DOCK_E_INVALID, "bucket %d bound must be %d", (int)b, L->buckets[b].upper);
-    if (x.lanes_per_pose != 1 && x.lanes_per_pose != 2) return set_err(DOCK_E_INVALID, "lanes_per_pose must be 1 or 2");
+    if (x.lanes_per_pose != 1 && x.lanes_per_pose != 2 && x.lanes_per_pose != 4)
+      return set_err(DOCK_E_INVALID, "lanes_per_pose must be 1, 2 or 4");
     if (x.waves_per_group < 0 || x.waves_per_group > kSearchMaxThreads / kWave)
       return set_err(DOCK_E_INVALID, "waves_per_group must be in 0..%d", kSearchMaxThreads / kWave);
   }
@@ -1016,7 +1017,7 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
     S.lds_atoms = B.lds_atoms;
     SearchShape best{0, 0};
     float best_ms = 0.f;
-    for (int lp = 1; lp <= 2 && e == hipSuccess; ++lp) {
+    for (int lp = 1; lp <= 4 && e == hipSuccess; lp *= 2) {
       const int max_w = std::min(kSearchMaxThreads / kWave, (P * lp + kWave - 1) / kWave);
       for (int w = 1; w <= max_w && e == hipSuccess; ++w) {
         const SearchShape shape{lp, w};

@@ -176,53 +176,54 @@ struct PairGroup {
   }
 };
 
-// Coordinates of both atoms of each pair of a group, from this lane's column.
-template <int STRIDE>
-struct GroupCoords {
-  float xi[4], yi[4], zi[4], xj[4], yj[4], zj[4];
-  __device__ __forceinline__ void load(const PairGroup &G, float *my) {
+// Record q R + u (u < R = 4 / LP) of four, for lane q of an LP-lane pose: the
+// lane picks its records out of the group's uniform ones.
+template <int LP>
+__device__ __forceinline__ PairRec lane_record(const PairRec r[4], int q, int u) {
+  if constexpr (LP == 1) {
+    return r[u];
+  } else if constexpr (LP == 2) {
+    const PairRec &a = r[u], &b = r[2 + u];
+    PairRec o;
+    o.ij = q ? b.ij : a.ij;
+    o.A = q ? b.A : a.A;
+    o.B = q ? b.B : a.B;
+    o.qq = q ? b.qq : a.qq;
+    o.sv = q ? b.sv : a.sv;
+    return o;
+  } else {
+    PairRec o = r[0];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = G.r[u].ij & 0xffff, j = G.r[u].ij >> 16;
-      xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
-      xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
+    for (int k = 1; k < 4; ++k) {
+      o.ij = q == k ? r[k].ij : o.ij;
+      o.A = q == k ? r[k].A : o.A;
+      o.B = q == k ? r[k].B : o.B;
+      o.qq = q == k ? r[k].qq : o.qq;
+      o.sv = q == k ? r[k].sv : o.sv;
     }
+    return o;
   }
-  // records 0 + 1 and records 2 + 3 of the group
-  __device__ __forceinline__ void energy(const FFConst &F, const PairGroup &G, float &s01, float &s23) const {
-    float e[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) e[u] = pair_term<false>(F, G.r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
-    s01 = e[0] + e[1];
-    s23 = e[2] + e[3];
-  }
-};
+}
 
-// Coordinates of the two pairs of a group that one lane of a two-lane pose
-// evaluates: records 2 h and 2 h + 1 for the lane's half h.
-template <int STRIDE>
-struct HalfGroupCoords {
-  float xi[2], yi[2], zi[2], xj[2], yj[2], zj[2];
-  PairRec r[2];
-  __device__ __forceinline__ void load(const PairGroup &G, float *my, bool h) {
+// The R = 4 / LP pairs of a group that lane q of an LP-lane pose evaluates
+// (records q R .. q R + R - 1), with their atoms' coordinates.
+template <int STRIDE, int LP>
+struct LaneGroupCoords {
+  static constexpr int R = 4 / LP;
+  float xi[R], yi[R], zi[R], xj[R], yj[R], zj[R];
+  PairRec r[R];
+  __device__ __forceinline__ void load(const PairGroup &G, float *my, int q) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const PairRec &a = G.r[u], &b = G.r[2 + u];
-      r[u].ij = h ? b.ij : a.ij;
-      r[u].A = h ? b.A : a.A;
-      r[u].B = h ? b.B : a.B;
-      r[u].qq = h ? b.qq : a.qq;
-      r[u].sv = h ? b.sv : a.sv;
+    for (int u = 0; u < R; ++u) {
+      r[u] = lane_record<LP>(G.r, q, u);
       const int i = r[u].ij & 0xffff, j = r[u].ij >> 16;
       xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
       xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
     }
   }
-  __device__ __forceinline__ float energy(const FFConst &F) const {
-    float e[2];
+  __device__ __forceinline__ void energy(const FFConst &F, float e[R]) const {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) e[u] = pair_term<false>(F, r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
-    return e[0] + e[1];
+    for (int u = 0; u < R; ++u) e[u] = pair_term<false>(F, r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
   }
 };
 
@@ -234,24 +235,26 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Energy of the pose whose gene j is g[j * gs] for ligand header H (uniform).
-// LP lanes build and score one pose together.  With LP = 2 the lanes of the two
-// halves of the wavefront (h = lane / 32) share the pose's LDS column and split
-// its atoms by parity and every pair group (records 2h and 2h + 1); lanes of one
-// pose exchange coordinates through LDS, ordered by wave_sync().  In both forms
-// the energy is accumulated as
-//   (inter over even atoms + records 0-1 of every group + even 12-10 pairs)
-//   + (inter over odd atoms + records 2-3 of every group + odd 12-10 pairs),
-// each part summed in index order, so LP = 1 and LP = 2 give the same bits.
-// Non-finite genes give NaN.
+// LP (1, 2 or 4) lanes build and score one pose together: lane h of the pose
+// is lane p + 64 h / LP of the wavefront.  The lanes share the pose's LDS
+// column (exchanging coordinates through LDS, ordered by wave_sync()) and split
+// its atoms, pair records and 12-10 pairs.  In every form the energy is
+//   (p0 + p1) + (p2 + p3),   p_u = inter over atoms i with i % 4 == u
+//                                + record u of every pair group
+//                                + 12-10 pairs p with p % 4 == u,
+// each p_u summed in index order (inter first, then the groups, then the 12-10
+// pairs); lane h owns p_u for u in [h 4/LP, (h + 1) 4/LP).  So every LP gives
+// the same bits.  Non-finite genes give NaN.
 template <int STRIDE, int LAYOUT, int LP = 1>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
                             const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my) {
-  static_assert(LP == 1 || LP == 2, "one or two lanes per pose");
+  static_assert(LP == 1 || LP == 2 || LP == 4, "one, two or four lanes per pose");
+  constexpr int R = 4 / LP;   // partial sums (and records of a group) per lane
   const int n = H.n_atoms;
   const float4 *__restrict__ atoms = L.atoms + H.atom_off;
   const int32_t *__restrict__ types = L.atom_type + H.atom_off;
-  const int h = LP == 2 ? (int)((threadIdx.x & 63) >> 5) : 0;
-  if (LP == 2) wave_sync();  // the column's previous pose has been read by both lanes
+  const int h = LP > 1 ? (int)((threadIdx.x & 63) / (64 / LP)) : 0;
+  if (LP > 1) wave_sync();  // the column's previous pose has been read by all its lanes
 
   // reference conformation (centred) into the pose's LDS column
   for (int i = h; i < n; i += LP) {
@@ -260,7 +263,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
     at<STRIDE>(my, i, 1) = a.y;
     at<STRIDE>(my, i, 2) = a.z;
   }
-  if (LP == 2) wave_sync();
+  if (LP > 1) wave_sync();
 
   bool bad = false;
   // Algorithm 1, rotatable bonds: rotate each fragment about its current bond
@@ -287,7 +290,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
       at<STRIDE>(my, i, 1) = ay + fmaf(r10, vx, fmaf(r11, vy, r12 * vz));
       at<STRIDE>(my, i, 2) = az + fmaf(r20, vx, fmaf(r21, vy, r22 * vz));
     }
-    if (LP == 2) wave_sync();
+    if (LP > 1) wave_sync();
   }
 
   // Algorithm 1, rigid part: rotate about the ligand origin, then translate
@@ -312,7 +315,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
     at<STRIDE>(my, i, 1) = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
     at<STRIDE>(my, i, 2) = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
   }
-  if (LP == 2) wave_sync();
+  if (LP > 1) wave_sync();
 
   // Algorithm 2: the inter-energy loop over atoms and the intra-energy loop over
   // pairs, interleaved.  Iteration k issues the map loads of the lane's atom of
@@ -324,12 +327,17 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   // groups to read past).
   const PairRec *__restrict__ pairs = L.pairs + H.pair_off;
   const int ng = H.n_groups;
-  const int slots = (n + LP - 1) / LP;   // atoms per lane (the last one may be absent)
-  float inter0 = 0.f, inter1 = 0.f, intra0 = 0.f, intra1 = 0.f;
+  // The lane's atoms in index order: slot k is atom 4 (k / R) + h R + k % R, of
+  // class h R + k % R; lane 0 has the most slots, the others skip their last.
+  const int slots = R * (n / 4) + min(n % 4, R);
+  auto atom_of = [&](int slot) { return 4 * (slot / R) + h * R + slot % R; };
+  float inter[R], intra[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) inter[u] = intra[u] = 0.f;
   // ring[d] holds the loads of the atom of slot k + d; fetched kGatherAhead slices early
   Corners<LAYOUT> ring[kGatherAhead + 1];
   auto gather = [&](int slot) {
-    const int i = min(slot * LP + h, n - 1);
+    const int i = min(atom_of(slot), n - 1);
     return gather_corners<LAYOUT>(G, maps, types[i], atoms[i].w, at<STRIDE>(my, i, 0), at<STRIDE>(my, i, 1),
                                   at<STRIDE>(my, i, 2));
   };
@@ -339,79 +347,58 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   PairGroup A, B;
   A.load(pairs);
   B.load(pairs + 4);
-  if constexpr (LP == 1) {
-    GroupCoords<STRIDE> X;
-    X.load(A, my);
-    for (int k = 0; k < n; ++k) {
-      const int ka = k + kGatherAhead;
-      if (ka < n) ring[kGatherAhead] = gather(ka);
-      const int g0 = (k * ng) / n, g1 = ((k + 1) * ng) / n;
-      for (int gi = g0; gi < g1; ++gi) {
-        GroupCoords<STRIDE> Xn;
-        Xn.load(B, my);
-        PairGroup C;
-        C.load(pairs + 4 * (gi + 2));
-        float s01, s23;
-        X.energy(F, A, s01, s23);
-        intra0 += s01;
-        intra1 += s23;
-        A = B;
-        B = C;
-        X = Xn;
-      }
-      const float v = interpolate_corners<LAYOUT>(ring[0]);
-      if (k & 1) inter1 += v;
-      else inter0 += v;
+  LaneGroupCoords<STRIDE, LP> X;
+  X.load(A, my, h);
+  for (int k = 0; k < slots; ++k) {
+    const int ka = k + kGatherAhead;
+    if (ka < slots) ring[kGatherAhead] = gather(ka);
+    const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
+    for (int gi = g0; gi < g1; ++gi) {
+      LaneGroupCoords<STRIDE, LP> Xn;
+      Xn.load(B, my, h);
+      PairGroup C;
+      C.load(pairs + 4 * (gi + 2));
+      float e[R];
+      X.energy(F, e);
 #pragma unroll
-      for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+      for (int u = 0; u < R; ++u) intra[u] += e[u];
+      A = B;
+      B = C;
+      X = Xn;
     }
-    const PairRec *__restrict__ hb = L.pairs + H.hb_off;
-    for (int p = 0; p < H.n_pairs_hb; ++p) {
-      const float e = pair_energy<true, STRIDE>(F, hb[p], my);
-      if (p & 1) intra1 += e;
-      else intra0 += e;
-    }
-    const float e = (inter0 + intra0) + (inter1 + intra1);
-    return bad ? __builtin_nanf("") : e;
-  } else {
-    HalfGroupCoords<STRIDE> X;
-    X.load(A, my, h);
-    for (int k = 0; k < slots; ++k) {
-      const int ka = k + kGatherAhead;
-      if (ka < slots) ring[kGatherAhead] = gather(ka);
-      const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
-      for (int gi = g0; gi < g1; ++gi) {
-        HalfGroupCoords<STRIDE> Xn;
-        Xn.load(B, my, h);
-        PairGroup C;
-        C.load(pairs + 4 * (gi + 2));
-        intra0 += X.energy(F);
-        A = B;
-        B = C;
-        X = Xn;
-      }
-      const float v = interpolate_corners<LAYOUT>(ring[0]);
-      if (k * 2 + h < n) inter0 += v;
+    const float v = interpolate_corners<LAYOUT>(ring[0]);
+    if (atom_of(k) < n) {
 #pragma unroll
-      for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+      for (int u = 0; u < R; ++u)
+        if (k % R == u) inter[u] += v;
     }
-    const PairRec *__restrict__ hb = L.pairs + H.hb_off;
-    const PairRec zero{0, 0.f, 0.f, 0.f, 0.f};
-    for (int p = 0; p < H.n_pairs_hb; p += 2) {
-      const PairRec ra = hb[p], rb = p + 1 < H.n_pairs_hb ? hb[p + 1] : zero;
-      PairRec r;
-      r.ij = h ? rb.ij : ra.ij;
-      r.A = h ? rb.A : ra.A;
-      r.B = h ? rb.B : ra.B;
-      r.qq = h ? rb.qq : ra.qq;
-      r.sv = h ? rb.sv : ra.sv;
-      intra0 += pair_energy<true, STRIDE>(F, r, my);
-    }
-    // this half's part, then the sum of both halves (the same on both lanes)
-    const float part = inter0 + intra0;
-    const float e = part + __shfl_xor(part, 32);
-    return bad ? __builtin_nanf("") : e;
+#pragma unroll
+    for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
   }
+  // 12-10 pairs, four at a time (past the end: all-zero records, which add +0)
+  const PairRec *__restrict__ hb = L.pairs + H.hb_off;
+  const PairRec zero{0, 0.f, 0.f, 0.f, 0.f};
+  for (int p = 0; p < H.n_pairs_hb; p += 4) {
+    PairRec blk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) blk[u] = p + u < H.n_pairs_hb ? hb[p + u] : zero;
+#pragma unroll
+    for (int u = 0; u < R; ++u) intra[u] += pair_energy<true, STRIDE>(F, lane_record<LP>(blk, h, u), my);
+  }
+  float part[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) part[u] = inter[u] + intra[u];
+  float e;
+  if constexpr (LP == 1) {
+    e = (part[0] + part[1]) + (part[2] + part[3]);
+  } else if constexpr (LP == 2) {
+    const float t = part[0] + part[1];
+    e = t + __shfl_xor(t, 32);
+  } else {
+    const float t = part[0] + __shfl_xor(part[0], 16);
+    e = t + __shfl_xor(t, 32);
+  }
+  return bad ? __builtin_nanf("") : e;
 }
 
 }  // namespace dock

@@ -123,8 +123,8 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
 // The whole search of one ligand, run by one workgroup.  The per-individual
 // steps without a pose (initial genotypes, DE trials, copies) use lane t for
 // individuals t, t + blockDim.x, ...; the scoring passes use LP lanes per
-// individual, the lanes of one individual in the two halves of a wavefront when
-// LP = 2.  The population is worked on in a gene-major copy W (gene j of
+// individual, lane p + 64 h / LP of a wavefront being lane h of its p-th
+// individual.  The population is worked on in a gene-major copy W (gene j of
 // individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
 // touch neighbouring words; the caller's individual-major population is read
 // at the start and written back at the end.
@@ -133,7 +133,7 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   constexpr int kStride = kWave / LP;   // individuals per wavefront in a scoring pass
   const int t = threadIdx.x, NT = blockDim.x;
   const int lane = t & (kWave - 1), wave = t / kWave;
-  const int h = LP == 2 ? lane >> 5 : 0;            // which lane of the individual
+  const int h = lane / kStride;                     // which lane of the individual
   const int sidx = wave * kStride + (lane & (kStride - 1));
   const int SNT = NT / LP;
   const LigHeader H = S.L.hdr[lig];
@@ -373,6 +373,7 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t w
 template <int LAYOUT>
 static hipError_t launch_search_lp(const SearchLaunch &S, int32_t n_cu, SearchShape shape, hipStream_t s,
                                    const char **step) {
+  if (shape.lanes_per_pose == 4) return launch_search_t<LAYOUT, 4>(S, n_cu, shape.waves, s, step);
   if (shape.lanes_per_pose == 2) return launch_search_t<LAYOUT, 2>(S, n_cu, shape.waves, s, step);
   return launch_search_t<LAYOUT, 1>(S, n_cu, shape.waves, s, step);
 }

@@ -166,8 +166,8 @@ def test_gen_reached(dk):
 
 
 def test_launch_shape_does_not_change_results(dk):
-    """One and two lanes per pose, and every wavefront count, give the same
-    search bit for bit (the energies sum the same partial sums in the same
+    """One, two and four lanes per pose, and every wavefront count, give the
+    same search bit for bit (the energies sum the same partial sums in the same
     order); the autotuner fixes a valid shape per bucket and changes nothing."""
     ff, rec, grid, maps = system(2, grid_n=48)
     atoms = [10, 14, 20, 31, 33, 40, 47, 52, 60, 70, 85, 96]
@@ -180,7 +180,7 @@ def test_launch_shape_does_not_change_results(dk):
     bounds = [b for b, _, _ in dk.dock_search_shapes(ligs)]
     assert bounds == [16, 32, 48, 64, 96]
     ref = None
-    for lp in (1, 2):
+    for lp in (1, 2, 4):
         for w in (0, 1, 2, 3):
             dk.dock_search_set_shapes(ligs, [(b, lp, w) for b in bounds])
             got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
@@ -190,23 +190,24 @@ def test_launch_shape_does_not_change_results(dk):
                 assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (lp, w)
     dk.dock_search_autotune(pocket, ligs, params, stride, tune_generations=2)
     for b, lp, w in dk.dock_search_shapes(ligs):
-        assert lp in (1, 2) and 1 <= w <= 4
+        assert lp in (1, 2, 4) and 1 <= w <= 4
     got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
     for x, y in zip(ref, got):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
     with pytest.raises(dk.DockError):
         dk.dock_search_set_shapes(ligs, [(b, 3, 0) for b in bounds])
-    # stopping at a target: the same generations and bests with one or two lanes per pose
+    # stopping at a target: the same generations and bests with one, two or four lanes per pose
     import torch
     target = torch.from_numpy(ref[3] + 0.1).cuda()
     reached = []
-    for lp in (1, 2):
+    for lp in (1, 2, 4):
         dk.dock_search_set_shapes(ligs, [(b, lp, 0) for b in bounds])
         stop = _params(dk, lo, hi, pop_size=75, n_generations=6, stop_at_target=1)
         r = _run_gpu_search(dk, pocket, ligs, stop, len(ligands), stride, target=target)
         reached.append((r[4].cpu().numpy(), r[3].cpu().numpy()))
-    np.testing.assert_array_equal(reached[0][0], reached[1][0])
-    np.testing.assert_array_equal(reached[0][1], reached[1][1])
+    for k in (1, 2):
+        np.testing.assert_array_equal(reached[0][0], reached[k][0])
+        np.testing.assert_array_equal(reached[0][1], reached[k][1])
     assert np.all((reached[0][0] >= 0) & (reached[0][0] <= 6))
     assert np.all(reached[0][1] <= ref[3] + 0.1)
 

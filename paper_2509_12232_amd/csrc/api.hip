@@ -1007,6 +1007,7 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
       std::lock_guard<std::mutex> g(g_shape_mu);
       auto it = g_shapes.find(shape_key(p, B, P));
       if (it != g_shapes.end()) {
+        std::lock_guard<std::mutex> guard(L->side_mu);
         B.lanes_per_pose = it->second.lanes_per_pose, B.waves = it->second.waves, B.fixed = 1;
         continue;
       }
@@ -1043,9 +1044,12 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
       }
     }
     if (e != hipSuccess || best.lanes_per_pose == 0) break;
-    B.lanes_per_pose = best.lanes_per_pose;
-    B.waves = best.waves;
-    B.fixed = 1;
+    {
+      std::lock_guard<std::mutex> guard(L->side_mu);
+      B.lanes_per_pose = best.lanes_per_pose;
+      B.waves = best.waves;
+      B.fixed = 1;
+    }
     std::lock_guard<std::mutex> g(g_shape_mu);
     g_shapes[shape_key(p, B, P)] = best;
   }

@@ -91,9 +91,22 @@ typedef struct {
  *   DOCK_LAYOUT_LINEAR  the ABI layout itself (1x memory);
  *   DOCK_LAYOUT_ZPAIR   node pairs along z, x-neighbours adjacent (2x);
  *   DOCK_LAYOUT_YZQUAD  node quads over y and z, x-neighbours adjacent (4x);
- *   DOCK_LAYOUT_AUTO    the yz-quad layout if its copy fits 240 MiB, else z-pair.
+ *   DOCK_LAYOUT_QUADLINE the yz-quads cut into 128-byte lines of eight
+ *                       x-consecutive quads that overlap by one, so a cell
+ *                       never straddles a line; the electrostatic and
+ *                       desolvation maps stored as E + D and E - D, of which
+ *                       an atom reads the one of its charge's sign (q E + |q| D
+ *                       is q (E + D) for q >= 0 and q (E - D) for q < 0): two
+ *                       cache lines per lookup (about 4.6x);
+ *   DOCK_LAYOUT_AUTO    the quad-line layout if its copy fits 512 MiB, else z-pair.
  * Results do not depend on the layout beyond float rounding of the same terms. */
-enum { DOCK_LAYOUT_AUTO = -1, DOCK_LAYOUT_LINEAR = 0, DOCK_LAYOUT_ZPAIR = 1, DOCK_LAYOUT_YZQUAD = 2 };
+enum {
+  DOCK_LAYOUT_AUTO = -1,
+  DOCK_LAYOUT_LINEAR = 0,
+  DOCK_LAYOUT_ZPAIR = 1,
+  DOCK_LAYOUT_YZQUAD = 2,
+  DOCK_LAYOUT_QUADLINE = 3
+};
 
 /* Create a pocket from precomputed maps (Sec. V: maps precomputed around the
  * receptor, AutoGrid-style).  maps: host (maps_on_device = 0) or device (1)
@@ -168,6 +181,19 @@ dock_status dock_destroy_ligands(dock_ligands *ligs);
 dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs,
                              const int32_t *pose_ligand, const float *genotypes, int32_t g_stride,
                              int64_t n_poses, float *energies, void *stream);
+
+/* Launch shape of dock_score_poses (a tuning knob; energies are bit-identical
+ * for every shape): lanes_per_pose = 1, 2 or 4 lanes build and score one pose
+ * together, a wavefront then holds 64 / lanes_per_pose poses and needs
+ * 1 / lanes_per_pose of the LDS, so more wavefronts stay resident for large
+ * ligands; 0 restores the automatic choice by the set's largest ligand.
+ * Process-wide; takes effect at the next call.  Errors: DOCK_E_INVALID for any
+ * other value. */
+dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose);
+
+/* The lanes per pose dock_score_poses uses for ligand set ligs (the setting
+ * above, or the automatic choice).  Errors: DOCK_E_INVALID (null argument). */
+dock_status dock_score_lanes_per_pose(const dock_ligands *ligs, int32_t *lanes_per_pose);
 
 /* Differential evolution (DE/rand/1/bin, greedy selection) as the evolutionary
  * search of Sec. V.  Random draws come from Philox4x64-10 (Salmon et al., SC'11)
@@ -369,20 +395,23 @@ dock_status dock_propose(const dock_ligands *ligs, const dock_mlp *net, const do
  * of its reference conformation placed rigidly with a random orientation and a
  * translation uniform in [box_lo, box_hi] (host float[3] each), through the
  * pocket's device layout and the scoring kernel's gather code, and writes the
- * sum of its values to out[lane] (device float[n_lanes]).  Timing it gives the
- * measured rate of random lookups for that workload's spatial distribution.
+ * sum of its values to out[lane] (device float[n_lanes]).  Each lane keeps
+ * in_flight (2, 4 or 8) lookups in flight: issues their loads, then
+ * interpolates them.  Timing it (at the fastest in_flight) gives the measured
+ * rate of random lookups for that workload's spatial distribution.
  * Errors: DOCK_E_INVALID (null pointers, handles of different devices, lig out
- * of range, empty box, n_lanes outside 1..2^31, per_lane not a positive
- * multiple of 4), DOCK_E_DEVICE. */
+ * of range, empty box, n_lanes outside 1..2^31, in_flight not 2, 4 or 8,
+ * per_lane not a positive multiple of in_flight), DOCK_E_DEVICE. */
 dock_status dock_gather_probe(const dock_pocket *pocket, const dock_ligands *ligs, int32_t lig,
                               const float box_lo[3], const float box_hi[3], int64_t n_lanes, int32_t per_lane,
-                              uint64_t seed, float *out, void *stream);
+                              int32_t in_flight, uint64_t seed, float *out, void *stream);
 
 /* Intra-energy pair terms alone (Algorithm 2's pair loop body) on register
  * coordinates: n_lanes lanes evaluate per_lane 12-6 pair terms each with the
  * pocket's force-field constants and write their sums to out[lane] (device
  * float[n_lanes]).  Timing it gives the measured VALU rate of pair terms.
- * Errors as dock_gather_probe. */
+ * Errors: DOCK_E_INVALID (null pointers, n_lanes outside 1..2^31, per_lane not
+ * a positive multiple of 4), DOCK_E_DEVICE. */
 dock_status dock_pair_probe(const dock_pocket *pocket, int64_t n_lanes, int32_t per_lane, float *out,
                             void *stream);
 

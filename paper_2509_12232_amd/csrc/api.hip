@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -39,27 +40,40 @@ extern "C" const char *dock_last_error(void) { return g_err; }
 extern "C" int32_t dock_version(void) { return 1; }
 
 // ------------------------------------------------------------------------------ handles
-// Packed layout for the scoring kernel: the yz-quad layout (4x the type maps,
-// the fewest cache lines per lookup) while its copy stays within kQuadBudget
-// bytes, so that it remains resident in the 256 MB Infinity Cache; else the
-// z-pair layout (2x).
-static constexpr double kQuadBudget = 240.0 * 1024 * 1024;
+// Packed layout for the scoring kernel: the quad-line layout (two cache lines
+// per lookup, about 4.6x the ABI maps) while its copy stays within kQuadBudget
+// bytes, so that the part the ligands reach stays resident in the 256 MB
+// Infinity Cache; else the z-pair layout (2x).
+static constexpr double kQuadBudget = 512.0 * 1024 * 1024;
+
+static int64_t line_blocks(const MapGeom &g) { return (g.nx - 2) / kLineCells + 1; }
+static int64_t line_stride(const MapGeom &g) {
+  return (int64_t)(g.nz - 1) * (g.ny - 1) * line_blocks(g) * kLineQuads;
+}
 
 static int32_t choose_layout(const MapGeom &g, int32_t requested) {
   if (requested != DOCK_LAYOUT_AUTO) return requested;
-  const double el = (double)g.nx * (g.ny - 1) * (g.nz - 1);
-  const double quad_bytes = el * 16.0 * g.n_types + el * 32.0;
-  return quad_bytes <= kQuadBudget ? kYZQuad : kZPair;
+  const double bytes = (double)line_stride(g) * 16.0 * (g.n_types + 2);
+  return bytes <= kQuadBudget ? kQuadLine : kZPair;
 }
 
 static bool valid_layout(int32_t layout) {
   return layout == DOCK_LAYOUT_AUTO || layout == DOCK_LAYOUT_LINEAR || layout == DOCK_LAYOUT_ZPAIR ||
-         layout == DOCK_LAYOUT_YZQUAD;
+         layout == DOCK_LAYOUT_YZQUAD || layout == DOCK_LAYOUT_QUADLINE;
 }
 
 // Builds the packed copy of p->maps (already on the device).
 static hipError_t pack_maps(dock_pocket *p, int32_t requested) {
   p->layout = choose_layout(p->geom, requested);
+  if (p->layout == kQuadLine) {
+    p->nxb = (int32_t)line_blocks(p->geom);
+    p->t_stride = line_stride(p->geom);
+    hipError_t e = hipMalloc(&p->tpack, (size_t)p->t_stride * 16 * (p->geom.n_types + 2));
+    if (e == hipSuccess)
+      e = launch_relayout_lines(p->geom, p->nxb, p->t_stride, p->maps, (float4 *)p->tpack, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    return e;
+  }
   if (p->layout != kZPair && p->layout != kYZQuad) return hipSuccess;  // kLinear reads p->maps directly
   const MapGeom &g = p->geom;
   const int py = p->layout == kYZQuad ? g.ny - 1 : g.ny;
@@ -102,7 +116,7 @@ static dock_status check_ff(const dock_forcefield *ff) {
   return DOCK_OK;
 }
 
-static dock_status check_grid(const dock_grid *g, int n_types) {
+static dock_status check_grid(const dock_grid *g, int n_types, int32_t layout) {
   if (!g) return set_err(DOCK_E_INVALID, "null grid");
   if (g->n_types != n_types) return set_err(DOCK_E_INVALID, "grid n_types %d != force field %d", g->n_types, n_types);
   for (int d = 0; d < 3; ++d)
@@ -112,6 +126,10 @@ static dock_status check_grid(const dock_grid *g, int n_types) {
     if (!isfinite(g->origin[d])) return set_err(DOCK_E_INVALID, "non-finite origin");
   const double total = (double)g->dims[0] * g->dims[1] * g->dims[2] * (n_types + 2);
   if (total > 2147483647.0) return set_err(DOCK_E_INVALID, "maps larger than 2^31 values");
+  // the quad-line gather indexes one map with 32-bit element indices
+  const double lines = (double)(g->dims[2] - 1) * (g->dims[1] - 1) * ((g->dims[0] - 2) / kLineCells + 1) * kLineQuads;
+  if (layout == DOCK_LAYOUT_QUADLINE && lines > 2147483647.0)
+    return set_err(DOCK_E_INVALID, "grid too large for the quad-line layout");
   return DOCK_OK;
 }
 
@@ -159,7 +177,7 @@ extern "C" dock_status dock_create_pocket(const dock_grid *grid, const float *ma
   if (!valid_layout(layout)) return set_err(DOCK_E_INVALID, "unknown layout %d", layout);
   dock_status st = check_ff(ff);
   if (st) return st;
-  if ((st = check_grid(grid, ff->n_types))) return st;
+  if ((st = check_grid(grid, ff->n_types, layout))) return st;
   if (!maps) return set_err(DOCK_E_INVALID, "null maps");
   DeviceScope ds(device);
   HIP_TRY(ds.err, "hipSetDevice");
@@ -190,7 +208,7 @@ extern "C" dock_status dock_create_pocket_from_receptor(const dock_grid *grid, c
   if (!valid_layout(layout)) return set_err(DOCK_E_INVALID, "unknown layout %d", layout);
   dock_status st = check_ff(ff);
   if (st) return st;
-  if ((st = check_grid(grid, ff->n_types))) return st;
+  if ((st = check_grid(grid, ff->n_types, layout))) return st;
   if (n_atoms < 0 || (n_atoms > 0 && (!xyz || !type || !charge)))
     return set_err(DOCK_E_INVALID, "bad receptor arrays");
   const int nt = ff->n_types;
@@ -559,6 +577,39 @@ extern "C" dock_status dock_destroy_ligands(dock_ligands *L) {
 }
 
 // ------------------------------------------------------------------------------ scoring
+// Lanes per pose of the scoring kernel: 0 = automatic (score_lanes_auto).
+static std::atomic<int32_t> g_score_lanes{0};
+
+// Automatic shape, from measurements on MI355X (config-1 maps, 4e6 poses, one
+// ligand of each size): up to 32 atoms the three shapes are within 1%; at 40
+// atoms two lanes are fastest (+16% over one: the one-lane wavefront's LDS, 3
+// floats per atom per pose, leaves five wavefronts per CU); above that four
+// lanes (+37% at 48 atoms, +106% at 96, where the pair terms dominate and are
+// split four ways).
+static int32_t score_lanes_auto(int32_t max_atoms) {
+  if (max_atoms <= 32) return 1;
+  if (max_atoms <= 40) return 2;
+  return 4;
+}
+
+static int32_t score_lanes(const dock_ligands *L) {
+  const int32_t lp = g_score_lanes.load();
+  return lp ? lp : score_lanes_auto(L->max_atoms);
+}
+
+extern "C" dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose) {
+  if (lanes_per_pose != 0 && lanes_per_pose != 1 && lanes_per_pose != 2 && lanes_per_pose != 4)
+    return set_err(DOCK_E_INVALID, "lanes_per_pose must be 0, 1, 2 or 4");
+  g_score_lanes.store(lanes_per_pose);
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_score_lanes_per_pose(const dock_ligands *L, int32_t *lanes_per_pose) {
+  if (!L || !lanes_per_pose) return set_err(DOCK_E_INVALID, "null argument");
+  *lanes_per_pose = score_lanes(L);
+  return DOCK_OK;
+}
+
 static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
   ScoreLaunch a{};
   a.L = L->view();
@@ -567,6 +618,7 @@ static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
   a.maps = p->view();
   a.layout = p->layout;
   a.lds_atoms = L->max_atoms;
+  a.lanes_per_pose = score_lanes(L);
   return a;
 }
 
@@ -1064,13 +1116,15 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
 // ------------------------------------------------------------------------------ probes
 extern "C" dock_status dock_gather_probe(const dock_pocket *p, const dock_ligands *L, int32_t lig,
                                          const float box_lo[3], const float box_hi[3], int64_t n_lanes,
-                                         int32_t per_lane, uint64_t seed, float *out, void *stream) {
+                                         int32_t per_lane, int32_t in_flight, uint64_t seed, float *out,
+                                         void *stream) {
   dock_status st = check_pair(p, L);
   if (st) return st;
   if (!box_lo || !box_hi || !out) return set_err(DOCK_E_INVALID, "null argument");
   if (lig < 0 || lig >= L->n_ligs) return set_err(DOCK_E_INVALID, "ligand index out of range");
-  if (n_lanes < 1 || n_lanes > ((int64_t)1 << 31) || per_lane < 4 || per_lane % 4)
-    return set_err(DOCK_E_INVALID, "n_lanes in 1..2^31, per_lane a positive multiple of 4");
+  if (in_flight != 2 && in_flight != 4 && in_flight != 8) return set_err(DOCK_E_INVALID, "in_flight must be 2, 4 or 8");
+  if (n_lanes < 1 || n_lanes > ((int64_t)1 << 31) || per_lane < in_flight || per_lane % in_flight)
+    return set_err(DOCK_E_INVALID, "n_lanes in 1..2^31, per_lane a positive multiple of in_flight");
   ProbeBox box{};
   for (int d = 0; d < 3; ++d) {
     if (!(box_lo[d] <= box_hi[d])) return set_err(DOCK_E_INVALID, "empty probe box");
@@ -1079,7 +1133,7 @@ extern "C" dock_status dock_gather_probe(const dock_pocket *p, const dock_ligand
   }
   DeviceScope ds(p->device);
   HIP_TRY(ds.err, "hipSetDevice");
-  HIP_TRY(launch_gather_probe(p->geom, p->view(), p->layout, L->view(), lig, box, n_lanes, per_lane,
+  HIP_TRY(launch_gather_probe(p->geom, p->view(), p->layout, L->view(), lig, box, n_lanes, per_lane, in_flight,
                               (uint32_t)seed, out, (hipStream_t)stream),
           "gather probe launch");
   return DOCK_OK;

@@ -59,15 +59,18 @@ struct dock_pocket {
   int64_t plane = 0;
   int32_t layout = dock::kLinear;    // layout the scoring kernel reads
   int32_t n_cu = 1;            // compute units of the device (persistent launch size)
-  void *tpack = nullptr;       // packed type maps
+  void *tpack = nullptr;       // packed type maps (kQuadLine: all maps)
   float4 *edpack = nullptr;    // packed electrostatic/desolvation records
   int64_t t_stride = 0;
+  int32_t nxb = 0;
   dock::MapData view() const {
     dock::MapData m{};
     m.lin = maps;
     m.t_stride = t_stride;
+    m.nxb = nxb;
     if (layout == dock::kZPair) m.tz = (const float2 *)tpack, m.edz = edpack;
     if (layout == dock::kYZQuad) m.tq = (const float4 *)tpack, m.edq = edpack;
+    if (layout == dock::kQuadLine) m.lq = (const float4 *)tpack;
     return m;
   }
 };

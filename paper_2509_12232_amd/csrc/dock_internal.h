@@ -59,7 +59,18 @@ struct MapGeom {
 //   kYZQuad: per type, float4 (M[x,y,z], M[x,y+1,z], M[x,y,z+1], M[x,y+1,z+1])
 //            over y < ny-1, z < nz-1; a cell is the two adjacent elements x, x+1
 //            (32 B).  Electrostatic + desolvation as two float4 quads per node.
-enum MapLayout : int32_t { kLinear = 0, kZPair = 1, kYZQuad = 2 };
+//   kQuadLine: the yz-quads of kYZQuad cut into 128-byte lines of eight
+//            x-consecutive quads, x = 7k .. 7k+7 in line k (consecutive lines
+//            of a row share one quad), so the two quads of a cell never straddle
+//            a line.  The electrostatic and desolvation maps are replaced by two
+//            signed maps S+ = E + D and S- = E - D: since q E + |q| D equals
+//            q S+ for q >= 0 and q S- for q < 0, one lookup reads a type quad pair
+//            and one signed quad pair, exactly two cache lines.
+enum MapLayout : int32_t { kLinear = 0, kZPair = 1, kYZQuad = 2, kQuadLine = 3 };
+
+// Quads per line of kQuadLine and the cells (x steps) a line covers.
+constexpr int kLineQuads = 8;
+constexpr int kLineCells = kLineQuads - 1;
 
 struct MapData {
   const float *lin;      // [n_types+2][nz][ny][nx]
@@ -67,7 +78,10 @@ struct MapData {
   const float4 *edz;     // kZPair E/D:    [nz-1][ny][nx]
   const float4 *tq;      // kYZQuad types: [n_types][nz-1][ny-1][nx]
   const float4 *edq;     // kYZQuad E/D:   [nz-1][ny-1][nx][2]
-  int64_t t_stride;      // elements per type map in the packed layout
+  const float4 *lq;      // kQuadLine:     [n_types + 2][nz-1][ny-1][nxb][kLineQuads], maps n_types and
+                         //                n_types+1 are S+ and S-
+  int64_t t_stride;      // elements (quads) per map in the packed layout
+  int32_t nxb;           // kQuadLine: lines per (y, z) row, (nx - 2) / kLineCells + 1
 };
 
 struct FFConst {
@@ -99,7 +113,8 @@ struct ScoreLaunch {
   int32_t g_stride;
   int64_t n_poses;
   float *energies;
-  int32_t lds_atoms;           // atom slots per lane in LDS
+  int32_t lds_atoms;           // atom slots per pose in LDS
+  int32_t lanes_per_pose;      // 1, 2 or 4
 };
 
 // Launchers (one translation unit per kernel family).

@@ -24,4 +24,8 @@ hipError_t launch_build_maps(const MapBuild &m, hipStream_t s);
 hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, void *types_out, float4 *ed_out,
                            hipStream_t s);
 
+// The kQuadLine copy: (n_types + 2) maps of t_stride quads, nxb lines per row.
+hipError_t launch_relayout_lines(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
+                                 hipStream_t s);
+
 }  // namespace dock

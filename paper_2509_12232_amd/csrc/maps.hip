@@ -106,6 +106,43 @@ __global__ void relayout_kernel(MapGeom g, int32_t layout, const float *__restri
   }
 }
 
+// kQuadLine: one thread per quad slot of one map; it writes that slot of every
+// map (types, then S+ = E + D and S- = E - D).  Slots past the row's last node
+// (x >= nx in a row's last line) are zero and never read.
+__global__ void relayout_lines_kernel(MapGeom g, int32_t nxb, int64_t t_stride, const float *__restrict__ lin,
+                                      float4 *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= t_stride) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int slot = (int)(e % kLineQuads);
+  const int64_t line = e / kLineQuads;
+  const int k = (int)(line % nxb);
+  const int y = (int)((line / nxb) % (ny - 1));
+  const int z = (int)(line / ((int64_t)nxb * (ny - 1)));
+  const int x = k * kLineCells + slot;
+  const int64_t plane = (int64_t)nx * ny * nz;
+  if (x >= nx) {
+    for (int m = 0; m < g.n_types + 2; ++m) out[m * t_stride + e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  auto quad = [&](int m) {
+    const float *M = lin + m * plane;
+    const int64_t o = ((int64_t)z * ny + y) * nx + x;
+    return make_float4(M[o], M[o + nx], M[o + (int64_t)nx * ny], M[o + (int64_t)nx * ny + nx]);
+  };
+  for (int t = 0; t < g.n_types; ++t) out[t * t_stride + e] = quad(t);
+  const float4 E = quad(g.n_types), D = quad(g.n_types + 1);
+  out[g.n_types * t_stride + e] = make_float4(E.x + D.x, E.y + D.y, E.z + D.z, E.w + D.w);
+  out[(g.n_types + 1) * t_stride + e] = make_float4(E.x - D.x, E.y - D.y, E.z - D.z, E.w - D.w);
+}
+
+hipError_t launch_relayout_lines(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(relayout_lines_kernel, dim3((unsigned)((t_stride + 255) / 256)), dim3(256), 0, s, g, nxb,
+                     t_stride, lin, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, void *types_out, float4 *ed_out,
                            hipStream_t s) {
   if (layout != kZPair && layout != kYZQuad) return hipErrorInvalidValue;

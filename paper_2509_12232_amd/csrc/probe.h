@@ -12,7 +12,7 @@ struct ProbeBox {
 
 hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const LigandsDev &L,
                                int32_t lig, const ProbeBox &box, int64_t n_lanes, int32_t per_lane,
-                               uint32_t seed, float *out, hipStream_t s);
+                               int32_t in_flight, uint32_t seed, float *out, hipStream_t s);
 hipError_t launch_pair_probe(const FFConst &F, int64_t n_lanes, int32_t per_lane, float *out, hipStream_t s);
 
 }  // namespace dock

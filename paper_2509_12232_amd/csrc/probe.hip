@@ -29,7 +29,7 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 __device__ __forceinline__ float unit01(uint32_t h) { return (float)(h >> 8) * (1.0f / 16777216.0f); }
 
-template <int LAYOUT>
+template <int LAYOUT, int U>
 __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M, LigandsDev L, int lig, ProbeBox box,
                                                             int per_lane, uint32_t seed, int64_t n_lanes,
                                                             float *out) {
@@ -39,8 +39,7 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
   const float4 *__restrict__ atoms = L.atoms + H.atom_off;
   const int32_t *__restrict__ types = L.atom_type + H.atom_off;
   float acc = 0.f;
-  constexpr int U = 4;  // lookups in flight per lane
-  for (int m = 0; m < per_lane; m += U) {
+  for (int m = 0; m < per_lane; m += U) {   // U lookups in flight per lane
     Corners<LAYOUT> c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -66,27 +65,33 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
   out[t] = acc;
 }
 
+template <int LAYOUT>
+static hipError_t launch_gather_probe_t(const MapGeom &G, const MapData &M, const LigandsDev &L, int32_t lig,
+                                        const ProbeBox &box, int64_t n_lanes, int32_t per_lane, int32_t in_flight,
+                                        uint32_t seed, float *out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n_lanes + 255) / 256);
+  void (*fn)(MapGeom, MapData, LigandsDev, int, ProbeBox, int, uint32_t, int64_t, float *);
+  switch (in_flight) {
+    case 2: fn = gather_probe_kernel<LAYOUT, 2>; break;
+    case 4: fn = gather_probe_kernel<LAYOUT, 4>; break;
+    case 8: fn = gather_probe_kernel<LAYOUT, 8>; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane, seed, n_lanes, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layout, const LigandsDev &L,
                                int32_t lig, const ProbeBox &box, int64_t n_lanes, int32_t per_lane,
-                               uint32_t seed, float *out, hipStream_t s) {
-  const unsigned blocks = (unsigned)((n_lanes + 255) / 256);
+                               int32_t in_flight, uint32_t seed, float *out, hipStream_t s) {
   switch (layout) {
-    case kLinear:
-      hipLaunchKernelGGL(gather_probe_kernel<kLinear>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
-                         seed, n_lanes, out);
-      break;
-    case kZPair:
-      hipLaunchKernelGGL(gather_probe_kernel<kZPair>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
-                         seed, n_lanes, out);
-      break;
-    case kYZQuad:
-      hipLaunchKernelGGL(gather_probe_kernel<kYZQuad>, dim3(blocks), dim3(256), 0, s, G, M, L, lig, box, per_lane,
-                         seed, n_lanes, out);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case kLinear: return launch_gather_probe_t<kLinear>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
+    case kZPair: return launch_gather_probe_t<kZPair>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
+    case kYZQuad: return launch_gather_probe_t<kYZQuad>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
+    case kQuadLine:
+      return launch_gather_probe_t<kQuadLine>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // Pair terms on coordinates held in registers: each lane evaluates per_lane pair

@@ -1,48 +1,63 @@
 // score.hip -- batched pose scoring kernel for gfx950.
 //
-// One 64-lane workgroup (one wavefront) scores 64 poses, one per lane.  Poses of
-// one ligand share every uniform load; a wavefront holding poses of several
-// ligands walks them one ligand at a time (each pass masks the other lanes).
+// One 64-lane workgroup (one wavefront) scores 64 / LP poses with LP = 1, 2 or 4
+// lanes per pose (the same bits for every LP).  Poses of one ligand share every
+// uniform load; a wavefront holding poses of several ligands walks them one
+// ligand at a time (each pass masks the other lanes).
 #include "dock_internal.h"
 #include "score_pose.h"
 
 namespace dock {
 
-template <int LAYOUT>
+template <int LAYOUT, int LP>
 __global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
+  constexpr int PPW = kWave / LP;  // poses per wavefront; lane p + PPW h is lane h of pose p
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
-  const int64_t pose = (int64_t)blockIdx.x * kWave + lane;
-  if (pose >= A.n_poses) return;
+  const int p = lane % PPW;
+  const int64_t pose = (int64_t)blockIdx.x * PPW + p;
+  if (pose >= A.n_poses) return;   // all LP lanes of a pose leave together
   int lig;
   if (A.poses_per_ligand > 0) lig = (int)(pose / A.poses_per_ligand);
   else lig = A.pose_ligand ? A.pose_ligand[pose] : 0;
   const bool valid = (lig >= 0) & (lig < A.L.n_ligs);
   float e = __builtin_nanf("");
   const float *g = A.genotypes + pose * (int64_t)A.g_stride;
-  float *my = lds + lane;
+  float *my = lds + p;
   uint64_t todo = __ballot(valid);
   while (todo) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
     const LigHeader H = A.L.hdr[cur];
-    if (valid && lig == cur) e = score_pose<kWave, LAYOUT>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
+    if (valid && lig == cur) e = score_pose<PPW, LAYOUT, LP>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
     todo &= ~__ballot(valid && lig == cur);
   }
-  A.energies[pose] = e;
+  if (lane < PPW) A.energies[pose] = e;
+}
+
+template <int LAYOUT, int LP>
+static hipError_t launch_score_lp(const ScoreLaunch &a, hipStream_t s) {
+  constexpr int PPW = kWave / LP;
+  const int64_t blocks = (a.n_poses + PPW - 1) / PPW;
+  const size_t lds = (size_t)a.lds_atoms * 3 * PPW * sizeof(float);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)score_kernel<LAYOUT, LP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  auto fn = score_kernel<LAYOUT, LP>;
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
+  return hipGetLastError();
 }
 
 template <int LAYOUT>
 static hipError_t launch_score_t(const ScoreLaunch &a, hipStream_t s) {
-  const int64_t blocks = (a.n_poses + kWave - 1) / kWave;
-  const size_t lds = (size_t)a.lds_atoms * 3 * kWave * sizeof(float);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)score_kernel<LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
+  switch (a.lanes_per_pose) {
+    case 1: return launch_score_lp<LAYOUT, 1>(a, s);
+    case 2: return launch_score_lp<LAYOUT, 2>(a, s);
+    case 4: return launch_score_lp<LAYOUT, 4>(a, s);
   }
-  hipLaunchKernelGGL(score_kernel<LAYOUT>, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
@@ -51,6 +66,7 @@ hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
     case kLinear: return launch_score_t<kLinear>(a, s);
     case kZPair: return launch_score_t<kZPair>(a, s);
     case kYZQuad: return launch_score_t<kYZQuad>(a, s);
+    case kQuadLine: return launch_score_t<kQuadLine>(a, s);
   }
   return hipErrorInvalidValue;
 }

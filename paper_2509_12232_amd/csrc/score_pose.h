@@ -70,6 +70,23 @@ struct Corners<kYZQuad> {
   }
 };
 
+template <>
+struct Corners<kQuadLine> {
+  float4 t0, t1, s0, s1;   // type and signed quads (y z, y+1 z, y z+1, y+1 z+1) at x and x+1
+  float fx, fy, fz, q, aq;
+  bool inside;
+  __device__ __forceinline__ void combine(float v[8]) const {
+    v[0] = fmaf(q, s0.x, t0.x);
+    v[1] = fmaf(q, s1.x, t1.x);
+    v[2] = fmaf(q, s0.y, t0.y);
+    v[3] = fmaf(q, s1.y, t1.y);
+    v[4] = fmaf(q, s0.z, t0.z);
+    v[5] = fmaf(q, s1.z, t1.z);
+    v[6] = fmaf(q, s0.w, t0.w);
+    v[7] = fmaf(q, s1.w, t1.w);
+  }
+};
+
 // Trilinear interpolation of (T_type + q E + |q| D) from loaded corners; 0 outside
 // the closed grid box (Algorithm 2's "nearby" test).
 template <int LAYOUT>
@@ -124,11 +141,19 @@ __device__ __forceinline__ Corners<LAYOUT> gather_corners(const MapGeom &G, cons
     const float2 *T = M.tz + (size_t)type * M.t_stride;
     C.t00 = T[e]; C.t10 = T[e + 1]; C.t01 = T[e + nx]; C.t11 = T[e + nx + 1];
     C.d00 = M.edz[e]; C.d10 = M.edz[e + 1]; C.d01 = M.edz[e + nx]; C.d11 = M.edz[e + nx + 1];
-  } else {
+  } else if constexpr (LAYOUT == kYZQuad) {
     const int e = cx + nx * (cy + (G.ny - 1) * cz);
     const float4 *T = M.tq + (size_t)type * M.t_stride;
     C.t0 = T[e]; C.t1 = T[e + 1];
     C.e0 = M.edq[2 * e]; C.d0 = M.edq[2 * e + 1]; C.e1 = M.edq[2 * e + 2]; C.d1 = M.edq[2 * e + 3];
+  } else {
+    // line k = cx / 7 of row (cy, cz), slot cx - 7k in [0, 6]: both quads in one line
+    const int k = cx / kLineCells;
+    const int e = ((cz * (G.ny - 1) + cy) * M.nxb + k) * kLineQuads + (cx - k * kLineCells);
+    const float4 *T = M.lq + (size_t)type * M.t_stride;
+    const float4 *Sg = M.lq + (size_t)(G.n_types + (q < 0.f ? 1 : 0)) * M.t_stride;
+    C.t0 = T[e]; C.t1 = T[e + 1];
+    C.s0 = Sg[e]; C.s1 = Sg[e + 1];
   }
   return C;
 }

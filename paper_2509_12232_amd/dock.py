@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 DOCK_OK, DOCK_E_INVALID, DOCK_E_NOMEM, DOCK_E_DEVICE, DOCK_E_UNSUPPORTED = range(5)
-DOCK_LAYOUT_AUTO, DOCK_LAYOUT_LINEAR, DOCK_LAYOUT_ZPAIR, DOCK_LAYOUT_YZQUAD = -1, 0, 1, 2
+DOCK_LAYOUT_AUTO, DOCK_LAYOUT_LINEAR, DOCK_LAYOUT_ZPAIR, DOCK_LAYOUT_YZQUAD, DOCK_LAYOUT_QUADLINE = -1, 0, 1, 2, 3
 _STATUS = {1: "DOCK_E_INVALID", 2: "DOCK_E_NOMEM", 3: "DOCK_E_DEVICE", 4: "DOCK_E_UNSUPPORTED"}
 
 
@@ -76,10 +76,12 @@ _SIGS = {
     "dock_ligand_pair_count": [_P, C.c_int32, _P],
     "dock_destroy_ligands": [_P],
     "dock_score_poses": [_P, _P, _P, _P, C.c_int32, C.c_int64, _P, _P],
+    "dock_score_set_lanes_per_pose": [C.c_int32],
+    "dock_score_lanes_per_pose": [_P, _P],
     "dock_de_init": [_P, _P, C.c_int32, _P, _P],
     "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
-    "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_uint64, _P, _P],
+    "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
     "dock_search_plan_create": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
     "dock_search_plan_launch": [_P, _P],
@@ -256,6 +258,17 @@ def dock_score_poses(pocket: Pocket, ligs: Ligands, genotypes, energies, pose_li
                                  _dptr(energies, "float32", "energies"), _stream(stream)))
 
 
+def dock_score_set_lanes_per_pose(lanes_per_pose: int):
+    """Lanes per pose of the scoring kernel (1, 2 or 4; 0 = automatic), process-wide."""
+    _check(_lib.dock_score_set_lanes_per_pose(int(lanes_per_pose)))
+
+
+def dock_score_lanes_per_pose(ligs: Ligands) -> int:
+    out = C.c_int32()
+    _check(_lib.dock_score_lanes_per_pose(ligs.handle, C.byref(out)))
+    return out.value
+
+
 @dataclass
 class SearchParams:
     pop_size: int
@@ -305,12 +318,13 @@ def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population,
 
 
 def dock_gather_probe(pocket: Pocket, ligs: Ligands, lig: int, box_lo, box_hi, out, per_lane: int, seed: int = 1,
-                      stream=None):
-    """Random map lookups alone (roofline probe); out: float32 device tensor, one value per lane."""
+                      stream=None, in_flight: int = 4):
+    """Random map lookups alone (roofline probe); out: float32 device tensor, one value per lane;
+    in_flight: lookups each lane keeps in flight (2, 4 or 8)."""
     lo = (C.c_float * 3)(*box_lo)
     hi = (C.c_float * 3)(*box_hi)
-    _check(_lib.dock_gather_probe(pocket.handle, ligs.handle, lig, lo, hi, int(out.numel()), per_lane, seed,
-                                  _dptr(out, "float32", "out"), _stream(stream)))
+    _check(_lib.dock_gather_probe(pocket.handle, ligs.handle, lig, lo, hi, int(out.numel()), per_lane, in_flight,
+                                  seed, _dptr(out, "float32", "out"), _stream(stream)))
 
 
 def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):

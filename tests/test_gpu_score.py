@@ -28,7 +28,7 @@ def _gpu_energies(dk, pocket, ligs, g, pose_ligand=None):
     return e.cpu().numpy()
 
 
-@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("layout", [0, 1, 2, 3])
 def test_config0_single_ligand_parity(dk, ora, layout):
     """24-atom, 6-torsion ligand on 40^3 maps: 4133 random poses (64 full tiles +
     a ragged tail), for each device map layout."""
@@ -45,6 +45,30 @@ def test_config0_single_ligand_parity(dk, ora, layout):
     keep = near_face_mask(ora, grid, [lig], g)
     assert keep.mean() > 0.95
     assert_energies_match(e_gpu, e_ref, keep)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (9, 3, 5), (16, 7, 4), (23, 11, 6)])
+def test_odd_grid_dims_every_layout(dk, ora, dims):
+    """Non-cubic grids whose x extent leaves the quad-line layout a partly
+    filled last line per row (and the 2-node minimum), with poses spread over
+    and past the grid box, for every device layout."""
+    import oracle
+    nt = 8
+    ff = synth.forcefield(nt)
+    rec = synth.make_receptor(3, 400, nt)
+    grid = synth.make_grid(dims, nt, spacing=1.0)
+    maps = oracle.build_maps(ff, rec, grid)
+    lig = synth.make_ligand(2, 0, 12, 3, nt)
+    lo = np.asarray(grid.origin) - 2.0
+    hi = np.asarray(grid.upper()) + 2.0
+    g = synth.sample_genotypes(21, 700, 3, 10, lo, hi)
+    e_ref = ora.score_poses(grid, maps, ff, [lig], g)
+    keep = near_face_mask(ora, grid, [lig], g)
+    for layout in (0, 1, 2, 3):
+        print("case: grid dims", dims, "layout", layout, flush=True)
+        pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+        ligs = dk.dock_create_ligands(pocket, [lig])
+        assert_energies_match(_gpu_energies(dk, pocket, ligs, g), e_ref, keep)
 
 
 def test_mixed_ligands_per_wave_with_hbond_and_solvation(dk, ora):
@@ -147,3 +171,39 @@ def test_deterministic_across_calls(dk):
     a = _gpu_energies(dk, pocket, ligs, g)
     b = _gpu_energies(dk, pocket, ligs, g)
     assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_lanes_per_pose_same_bits(dk, ora):
+    """Every scoring launch shape (1, 2 or 4 lanes per pose) gives the same bits,
+    on ligands of 1-96 atoms mixed across wavefronts with a ragged pose count;
+    the one-lane shape also matches the oracle."""
+    ff, rec, grid, maps = system(2, grid_n=48, solpar=-0.0011, hbond=True)
+    sizes = [(1, 0), (7, 1), (24, 6), (40, 10), (61, 12), (96, 20)]
+    ligands = [synth.make_ligand(4, i, a, t, 8) for i, (a, t) in enumerate(sizes)]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    lo, hi = synth.pocket_box(grid, half=4.0)
+    rng = np.random.default_rng(9)
+    n = 1001
+    pl = rng.integers(0, len(ligands), n).astype(np.int32)
+    g = synth.sample_genotypes(13, n, stride - 7, stride, lo, hi)
+    for p in range(n):
+        g[p, 7 + ligands[pl[p]].n_torsions:] = 0
+    runs = {}
+    try:
+        for lp in (1, 2, 4):
+            print("case: scoring lanes per pose", lp, flush=True)
+            dk.dock_score_set_lanes_per_pose(lp)
+            assert dk.dock_score_lanes_per_pose(ligs) == lp
+            runs[lp] = _gpu_energies(dk, pocket, ligs, g, pl)
+    finally:
+        dk.dock_score_set_lanes_per_pose(0)
+    np.testing.assert_array_equal(runs[2], runs[1])
+    np.testing.assert_array_equal(runs[4], runs[1])
+    sub = np.arange(0, n, 7)
+    e_ref = ora.score_poses(grid, maps, ff, ligands, g[sub], pose_ligand=pl[sub])
+    keep = near_face_mask(ora, grid, ligands, g[sub], pl[sub])
+    assert_energies_match(runs[1][sub], e_ref, keep)
+    with pytest.raises(dk.DockError):
+        dk.dock_score_set_lanes_per_pose(3)

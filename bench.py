@@ -97,8 +97,9 @@ def recorded_traffic(n_poses: int):
 
 def probes(S, kernel_ms: float, n_poses: int):
     """Measured ceilings at the same spatial distribution: map lookups alone
-    (gather probe: random rigid placements of the ligand's atoms with
-    translations in the pocket box) and pair terms alone (pair probe)."""
+    (gather probe: random rigid placements of the whole ligand, translations in
+    the pocket box, its atoms looked up in order) and pair terms alone (pair
+    probe)."""
     import torch
     dk = S["dk"]
     lig = S["lig"]
@@ -138,7 +139,8 @@ def probes(S, kernel_ms: float, n_poses: int):
     return {
         "gather": {"unit": "lookups/s", "kernel": round(kernel_lps, -6), "probe": round(probe_lps, -6),
                    "frac": round(kernel_lps / probe_lps, 4), "probe_form": probe_form,
-                   "probe_kind": "rigid random placements of the ligand's atoms, translations in the pocket box"},
+                   "probe_kind": "rigid random placements of the whole ligand, its atoms looked up in order, "
+                                 "translations in the pocket box"},
         "pairs": {"unit": "pair terms/s", "kernel": round(kernel_pps, -6), "probe": round(probe_pps, -6),
                   "frac": round(kernel_pps / probe_pps, 4)},
     }
@@ -161,9 +163,33 @@ def cpu_baseline(S, target_seconds: float, max_poses: int):
         if t >= target_seconds or n >= max_poses:
             break
         n = min(max_poses, int(n * max(2.0, 1.2 * target_seconds / max(t, 1e-3))))
+    # one core, on a prefix sized to about a tenth of the threaded run's time
+    n1 = max(200, int(n / threads / 10))
+    t0 = time.perf_counter()
+    oracle.score_poses(S["grid"], maps, S["ff"], [S["lig"]], S["g"][:n1], n_threads=1)
+    t1 = time.perf_counter() - t0
     return {"value": n / t, "unit": "poses/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of the 1e7 genotypes, scored in {t:.1f} s (FP64, {threads} threads)",
+            "one_core": {"value": round(n1 / t1, 1), "unit": "poses/s", "sample": f"first {n1} genotypes, {t1:.1f} s"},
+            "host": host_info(),
             "search": cpu_search_baseline(threads)}
+
+
+def host_info():
+    """CPU model, logical CPUs and the current clock of the host (from /proc/cpuinfo)."""
+    model, mhz = None, []
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k == "model name" and model is None:
+                model = v.strip()
+            elif k == "cpu MHz":
+                mhz.append(float(v))
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "mean_mhz": round(float(np.mean(mhz)), 0) if mhz else None}
 
 
 def cpu_search_baseline(threads: int):
@@ -377,7 +403,8 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    kernel_ms = float(np.mean(step_ms))
     ms_per_step = wall * 1e3 / args.steps
     n = args.poses
     value = n / (wall / args.steps)
@@ -394,6 +421,7 @@ def main():
                 "frac": round(gather_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
                 "lanes_per_pose": S["dk"].dock_score_lanes_per_pose(S["ligs"]),
+                "kernel_ms_sd": round(float(np.std(step_ms)), 4), "kernel_ms_min": round(float(np.min(step_ms)), 4),
                 "alu": {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},
                 "measured": probes(S, kernel_ms, n)}

@@ -391,11 +391,12 @@ dock_status dock_propose(const dock_ligands *ligs, const dock_mlp *net, const do
 /* ---- Roofline probes: measurement aids, not steps of the docking path. ---- */
 
 /* Map lookups alone, as the inter-energy loop of Algorithm 2 performs them: each
- * of n_lanes lanes interpolates per_lane atoms of ligand lig, each a random atom
- * of its reference conformation placed rigidly with a random orientation and a
- * translation uniform in [box_lo, box_hi] (host float[3] each), through the
- * pocket's device layout and the scoring kernel's gather code, and writes the
- * sum of its values to out[lane] (device float[n_lanes]).  Each lane keeps
+ * of n_lanes lanes interpolates per_lane atoms of ligand lig: its reference
+ * conformation placed rigidly with a random orientation and a translation
+ * uniform in [box_lo, box_hi] (host float[3] each), atoms in index order, then
+ * the next placement, through the pocket's device layout and the scoring
+ * kernel's gather code, and writes the sum of its values to out[lane] (device
+ * float[n_lanes]).  Each lane keeps
  * in_flight (2, 4 or 8) lookups in flight: issues their loads, then
  * interpolates them.  Timing it (at the fastest in_flight) gives the measured
  * rate of random lookups for that workload's spatial distribution.

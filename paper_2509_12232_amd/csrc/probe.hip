@@ -1,12 +1,12 @@
 // probe.hip -- roofline probes for the scoring kernel's two halves.
 //
 // gather_probe: the inter-energy lookups alone (Algorithm 2's map lookups):
-// each lane interpolates atoms of one ligand placed rigidly at random (a
-// translation uniform in a box, a random orientation, a random atom of the
-// ligand's reference conformation), through the same layout and gather code
-// as the scoring kernel, at full occupancy and with no other work.  Its rate
-// is the measured ceiling for the lookups of that workload's spatial
-// distribution (torsional flexibility aside).
+// each lane places one ligand rigidly at random (a translation uniform in a
+// box, a random orientation) and interpolates its atoms in index order, then
+// the next placement, through the same layout and gather code as the scoring
+// kernel, at full occupancy and with no other work.  Its rate is the measured
+// ceiling for the lookups of that workload's spatial distribution (torsional
+// flexibility aside).
 //
 // pair_probe: the intra-energy pair term alone on register-resident
 // coordinates, at full occupancy: the measured VALU ceiling for pair terms.
@@ -43,7 +43,10 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
     Corners<LAYOUT> c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t h = mix32(seed ^ mix32(t * 0x9E3779B9u + (uint32_t)(m + u)));
+      // lookup m + u is atom (m + u) % n of placement (m + u) / n
+      const uint32_t place = (uint32_t)(m + u) / (uint32_t)H.n_atoms;
+      const int i = (int)((uint32_t)(m + u) - place * (uint32_t)H.n_atoms);
+      const uint32_t h = mix32(seed ^ mix32(t * 0x9E3779B9u + place));
       const float tx = box.lo[0] + box.ext[0] * unit01(mix32(h + 1));
       const float ty = box.lo[1] + box.ext[1] * unit01(mix32(h + 2));
       const float tz = box.lo[2] + box.ext[2] * unit01(mix32(h + 3));
@@ -52,7 +55,6 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(MapGeom G, MapData M,
       float qy = 2.f * unit01(mix32(h + 6)) - 1.f, qz = 2.f * unit01(mix32(h + 7)) - 1.f;
       const float r = __builtin_amdgcn_rsqf(fmaxf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))), 1e-12f));
       qw *= r; qx *= r; qy *= r; qz *= r;
-      const int i = (int)(h % (uint32_t)H.n_atoms);
       const float4 a = atoms[i];
       const float px = fmaf(1.f - 2.f * (qy * qy + qz * qz), a.x, fmaf(2.f * (qx * qy - qw * qz), a.y, fmaf(2.f * (qx * qz + qw * qy), a.z, tx)));
       const float py = fmaf(2.f * (qx * qy + qw * qz), a.x, fmaf(1.f - 2.f * (qx * qx + qz * qz), a.y, fmaf(2.f * (qy * qz - qw * qx), a.z, ty)));

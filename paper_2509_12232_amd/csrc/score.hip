@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
     const LigHeader H = A.L.hdr[cur];
-    if (valid && lig == cur) e = score_pose<PPW, LAYOUT, LP>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
+    // map loads two atoms ahead with one or two lanes per pose (measured faster
+    // on MI355X; with four lanes the extra registers cost more than they hide)
+    if (valid && lig == cur) e = score_pose<PPW, LAYOUT, LP, LP <= 2 ? 2 : 1>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
     todo &= ~__ballot(valid && lig == cur);
   }
   if (lane < PPW) A.energies[pose] = e;

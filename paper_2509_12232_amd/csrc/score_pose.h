@@ -1,13 +1,13 @@
 // score_pose.h -- device code that builds one pose from its genotype and scores
-// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one or two lanes per
-// pose.
+// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one, two or four lanes
+// per pose.
 //
-// Mapping: a lane (or a pair of lanes in the two halves of a wavefront) owns a
-// pose.  All ligand data (atoms, torsions, pairs) is uniform across the
-// wavefront and arrives through scalar loads, so every loop below is a scalar
-// loop.  The pose's atom coordinates live in an LDS column: coordinate c of
-// atom i at my[(3 i + c) * STRIDE], STRIDE = poses sharing one LDS row, which
-// makes every LDS access of a wavefront hit consecutive dwords.
+// Mapping: a lane (or LP = 2 or 4 lanes, one in each half or quarter of the
+// wavefront) owns a pose.  All ligand data (atoms, torsions, pairs) is uniform
+// across the wavefront and arrives through scalar loads, so every loop below is
+// a scalar loop.  The pose's atom coordinates live in an LDS column: coordinate
+// c of atom i at my[(3 i + c) * STRIDE], STRIDE = poses sharing one LDS row, so
+// the lanes that read the same atom hit consecutive dwords.
 #pragma once
 #include "dock_internal.h"
 
@@ -15,8 +15,6 @@ namespace dock {
 
 __device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-// How many pair slices ahead of its use an atom's map loads are issued.
-constexpr int kGatherAhead = 1;
 
 // Raw map values of one atom's grid cell, as loaded for the layout, plus what
 // is needed to finish the interpolation later.  v[b] of the combined value is
@@ -269,8 +267,10 @@ __device__ __forceinline__ void wave_sync() {
 //                                + 12-10 pairs p with p % 4 == u,
 // each p_u summed in index order (inter first, then the groups, then the 12-10
 // pairs); lane h owns p_u for u in [h 4/LP, (h + 1) 4/LP).  So every LP gives
-// the same bits.  Non-finite genes give NaN.
-template <int STRIDE, int LAYOUT, int LP = 1>
+// the same bits.  Non-finite genes give NaN.  AHEAD: how many pair slices ahead
+// of its use an atom's map loads are issued (more loads in flight, more
+// registers); it does not change the result.
+template <int STRIDE, int LAYOUT, int LP = 1, int AHEAD = 1>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
                             const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my) {
   static_assert(LP == 1 || LP == 2 || LP == 4, "one, two or four lanes per pose");
@@ -359,15 +359,15 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   float inter[R], intra[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) inter[u] = intra[u] = 0.f;
-  // ring[d] holds the loads of the atom of slot k + d; fetched kGatherAhead slices early
-  Corners<LAYOUT> ring[kGatherAhead + 1];
+  // ring[d] holds the loads of the atom of slot k + d; fetched AHEAD slices early
+  Corners<LAYOUT> ring[AHEAD + 1];
   auto gather = [&](int slot) {
     const int i = min(atom_of(slot), n - 1);
     return gather_corners<LAYOUT>(G, maps, types[i], atoms[i].w, at<STRIDE>(my, i, 0), at<STRIDE>(my, i, 1),
                                   at<STRIDE>(my, i, 2));
   };
 #pragma unroll
-  for (int d = 0; d < kGatherAhead; ++d)
+  for (int d = 0; d < AHEAD; ++d)
     if (d < slots) ring[d] = gather(d);
   PairGroup A, B;
   A.load(pairs);
@@ -375,8 +375,8 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   LaneGroupCoords<STRIDE, LP> X;
   X.load(A, my, h);
   for (int k = 0; k < slots; ++k) {
-    const int ka = k + kGatherAhead;
-    if (ka < slots) ring[kGatherAhead] = gather(ka);
+    const int ka = k + AHEAD;
+    if (ka < slots) ring[AHEAD] = gather(ka);
     const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
     for (int gi = g0; gi < g1; ++gi) {
       LaneGroupCoords<STRIDE, LP> Xn;
@@ -398,7 +398,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
         if (k % R == u) inter[u] += v;
     }
 #pragma unroll
-    for (int d = 0; d < kGatherAhead; ++d) ring[d] = ring[d + 1];
+    for (int d = 0; d < AHEAD; ++d) ring[d] = ring[d + 1];
   }
   // 12-10 pairs, four at a time (past the end: all-zero records, which add +0)
   const PairRec *__restrict__ hb = L.pairs + H.hb_off;

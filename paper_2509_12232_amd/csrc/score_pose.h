@@ -291,13 +291,19 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   if (LP > 1) wave_sync();
 
   bool bad = false;
+  // the genes are requested before they are needed: the rigid ones here, each
+  // torsion angle one torsion ahead
+  const float tx = g[0], ty = g[gs], tz = g[2 * gs];
+  float qw = g[3 * gs], qx = g[4 * gs], qy = g[5 * gs], qz = g[6 * gs];
   // Algorithm 1, rotatable bonds: rotate each fragment about its current bond
   // axis.  Rotations about current axes commute on a tree, so the torsion order
   // of the genotype is used as is.
   const TorRec *__restrict__ tors = L.tors + H.tor_off;
+  float th_next = H.n_tors > 0 ? g[(7 + tors[0].gene) * gs] : 0.f;
   for (int k = 0; k < H.n_tors; ++k) {
     const TorRec T = tors[k];
-    const float th = g[(7 + T.gene) * gs];
+    const float th = th_next;
+    if (k + 1 < H.n_tors) th_next = g[(7 + tors[k + 1].gene) * gs];
     bad |= !__builtin_isfinite(th);
     const float ax = at<STRIDE>(my, T.a, 0), ay = at<STRIDE>(my, T.a, 1), az = at<STRIDE>(my, T.a, 2);
     float ux = at<STRIDE>(my, T.lo, 0) - ax, uy = at<STRIDE>(my, T.lo, 1) - ay, uz = at<STRIDE>(my, T.lo, 2) - az;
@@ -319,8 +325,6 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   }
 
   // Algorithm 1, rigid part: rotate about the ligand origin, then translate
-  const float tx = g[0], ty = g[gs], tz = g[2 * gs];
-  float qw = g[3 * gs], qx = g[4 * gs], qy = g[5 * gs], qz = g[6 * gs];
   bad |= !(__builtin_isfinite(tx) & __builtin_isfinite(ty) & __builtin_isfinite(tz) & __builtin_isfinite(qw) &
            __builtin_isfinite(qx) & __builtin_isfinite(qy) & __builtin_isfinite(qz));
   const float nn = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));

@@ -66,7 +66,13 @@ __device__ __forceinline__ int pick_partner(DrawStream &s, int pop, int t0, int 
 }
 
 // Trial i of generation gen.  Gene j of population row r is pop[r * rs + j * gs];
-// gene j of the trial goes to trial[j * tgs].
+// gene j of the trial goes to trial[j * tgs].  The crossover draws (one per gene
+// of the ligand, in gene order) are taken first; the genes are then done in
+// blocks of eight whose loads are all issued before their arithmetic, so a
+// trial waits for memory once per block rather than once per gene.
+static_assert(7 + kMaxTorsions <= 64, "crossover decisions fit one 64-bit mask");
+constexpr int kGeneBlock = 8;
+
 __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen, int i, int g_stride,
                                  const float *__restrict__ pop, int rs, int gs, float *__restrict__ trial, int tgs) {
 #pragma clang fp contract(off)
@@ -79,28 +85,58 @@ __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen,
   const float *xi = pop + (size_t)i * rs, *x1 = pop + (size_t)r1 * rs;
   const float *x2 = pop + (size_t)r2 * rs, *x3 = pop + (size_t)r3 * rs;
   DrawStream c(p.seed, (uint64_t)i, (uint64_t)gen, (uint64_t)lig, kPurposeCross);
-  for (int j = 0; j < g_stride; ++j) {
-    float v = 0.f;
-    if (j < n_genes) {
-      const double u = c.unit();
-      if (u < (double)p.CR || j == jrand) {
-        const double diff = (double)x2[j * gs] - (double)x3[j * gs];
-        const double step = (double)p.F * diff;
-        v = (float)((double)x1[j * gs] + step);
-      } else {
-        v = xi[j * gs];
-      }
-      if (j < 3) {
-        if ((double)v < p.lo[j]) v = (float)p.lo[j];
-        if ((double)v > p.hi[j]) v = (float)p.hi[j];
-      } else if (j >= 7) {
-        double w = (double)v;
-        if (w > kPi) w = w - 2.0 * kPi;
-        else if (w <= -kPi) w = w + 2.0 * kPi;
-        v = (float)w;
-      }
+  uint64_t take = 0;   // bit j: gene j takes the mutant value
+  for (int j = 0; j < n_genes; ++j) {
+    const double u = c.unit();
+    if (u < (double)p.CR || j == jrand) take |= 1ull << j;
+  }
+  for (int j0 = 0; j0 < g_stride; j0 += kGeneBlock) {
+    float a1[kGeneBlock], a2[kGeneBlock], a3[kGeneBlock], ai[kGeneBlock];
+#pragma unroll
+    for (int k = 0; k < kGeneBlock; ++k) {
+      const int j = min(j0 + k, g_stride - 1);   // past the row: a valid gene, not used
+      a1[k] = x1[j * gs]; a2[k] = x2[j * gs]; a3[k] = x3[j * gs]; ai[k] = xi[j * gs];
     }
-    trial[j * tgs] = v;
+#pragma unroll
+    for (int k = 0; k < kGeneBlock; ++k) {
+      const int j = j0 + k;
+      if (j >= g_stride) break;
+      float v = 0.f;
+      if (j < n_genes) {
+        if ((take >> j) & 1) {
+          const double diff = (double)a2[k] - (double)a3[k];
+          const double step = (double)p.F * diff;
+          v = (float)((double)a1[k] + step);
+        } else {
+          v = ai[k];
+        }
+        if (j < 3) {
+          if ((double)v < p.lo[j]) v = (float)p.lo[j];
+          if ((double)v > p.hi[j]) v = (float)p.hi[j];
+        } else if (j >= 7) {
+          double w = (double)v;
+          if (w > kPi) w = w - 2.0 * kPi;
+          else if (w <= -kPi) w = w + 2.0 * kPi;
+          v = (float)w;
+        }
+      }
+      trial[j * tgs] = v;
+    }
+  }
+}
+
+// Copies genes j = h, h + LP, ... (< G) of a gene-major individual from src to
+// dst (element j at [j * P]), in blocks whose loads are issued before the stores.
+template <int LP>
+__device__ __forceinline__ void copy_genes(const float *__restrict__ src, float *__restrict__ dst, int h, int G,
+                                           int P) {
+  for (int j0 = h; j0 < G; j0 += kGeneBlock * LP) {
+    float v[kGeneBlock];
+#pragma unroll
+    for (int k = 0; k < kGeneBlock; ++k) v[k] = src[min(j0 + k * LP, G - 1) * P];
+#pragma unroll
+    for (int k = 0; k < kGeneBlock; ++k)
+      if (j0 + k * LP < G) dst[(j0 + k * LP) * P] = v[k];
   }
 }
 
@@ -215,7 +251,7 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
         const float e = score(T + i, P);
         float ei = E[i];
         if (e <= ei) {
-          for (int j = h; j < G; j += LP) W[j * P + i] = T[j * P + i];
+          copy_genes<LP>(T + i, W + i, h, G, P);
           ei = e;
           E[i] = e;  // (both lanes of an individual store the same value)
         }

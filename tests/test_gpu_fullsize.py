@@ -1,8 +1,15 @@
-"""Full-size parity for the scoring microbenchmark workload (10^7 random poses of
-one 40-atom, 10-torsion ligand on fourteen 100^3 maps), in the launch
-configuration the benchmark times: every pose is scored on the GPU, a seeded
-random sample is scored by the FP64 oracle, and properties that hold at any
-size are checked on all of them."""
+"""Full-size parity, in the launch configurations the benchmark times.
+
+Scoring microbenchmark (10^7 random poses of one 40-atom, 10-torsion ligand on
+fourteen 100^3 maps): every pose is scored on the GPU, a seeded random sample is
+scored by the FP64 oracle, and properties that hold at any size are checked on
+all of them.
+
+Uneven batch (10,000 ligands of 8-96 atoms, fourteen 80^3 maps, population 150
+x 300 generations, autotuned persistent launch, plain and with proposal rounds,
+eager and captured in a graph): for ligands sampled from every size bucket the
+oracle re-scores the best genotype and sampled members of the final population;
+on every ligand the best must be the first minimum of its final population."""
 import numpy as np
 import pytest
 
@@ -52,3 +59,101 @@ def test_config1_full_size_sampled_parity(ora):
     dk.dock_score_poses(pocket, ligs, torch.from_numpy(g[idx]).cuda(), e2)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(e2.cpu().numpy(), e_all[idx])
+
+
+N_LIGANDS = 10_000
+
+
+@pytest.fixture(scope="module")
+def batch3(ora):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_2509_12232_amd import dock as dk
+    c = synth.CONFIGS[3]
+    nt = c["n_types"]
+    ff = synth.forcefield(nt)
+    rec = synth.make_receptor(1, 2000, nt)
+    grid = synth.make_grid(c["grid_n"], nt)
+    print("case: config3 full size, oracle maps 80^3, 10000 ligands", flush=True)
+    maps = ora.build_maps(ff, rec, grid)
+    ligands = synth.config_ligands(3, workers=16)
+    assert len(ligands) == N_LIGANDS
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    L = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    params = dk.SearchParams(pop_size=c["pop"], n_generations=c["gens"], seed=1, box_lo=tuple(lo),
+                             box_hi=tuple(hi))
+    dk.dock_search_autotune(pocket, L, params, stride, tune_generations=3)
+    return dict(dk=dk, ff=ff, grid=grid, maps=maps, ligands=ligands, pocket=pocket, L=L, stride=stride,
+                params=params)
+
+
+def _buffers(n, pop, stride):
+    import torch
+    f32 = dict(dtype=torch.float32, device="cuda")
+    return (torch.zeros((n, pop, stride), **f32), torch.zeros((n, pop), **f32), torch.zeros((n, stride), **f32),
+            torch.zeros(n, **f32))
+
+
+def _check_search_sample(ora, b, out, what, seed):
+    pop, pe, bg, be = (x.cpu().numpy() for x in out)
+    n = len(b["ligands"])
+    # any size: the reported best is the first minimum of each final population
+    assert np.isfinite(pe).all()
+    np.testing.assert_array_equal(be, pe.min(axis=1))
+    np.testing.assert_array_equal(bg, pop[np.arange(n), pe.argmin(axis=1)])
+    # sampled: five ligands per atom-count bucket and the first and last ligand
+    rng = np.random.default_rng(seed)
+    atoms = np.array([l.n_atoms for l in b["ligands"]])
+    picks = {0, n - 1}
+    for lo_a, hi_a in ((1, 16), (17, 32), (33, 48), (49, 64), (65, 96)):
+        ids = np.nonzero((atoms >= lo_a) & (atoms <= hi_a))[0]
+        picks.update(int(x) for x in rng.choice(ids, min(5, len(ids)), replace=False))
+    picks = sorted(picks)
+    sub = [b["ligands"][k] for k in picks]
+    geno, energy, pl = [], [], []
+    for s_i, k in enumerate(picks):
+        members = rng.choice(pop.shape[1], 8, replace=False)
+        geno += [bg[k]] + [pop[k, m] for m in members]
+        energy += [be[k]] + [pe[k, m] for m in members]
+        pl += [s_i] * 9
+    geno = np.asarray(geno, np.float32)
+    pl = np.asarray(pl, np.int32)
+    ref = ora.score_poses(b["grid"], b["maps"], b["ff"], sub, geno, pose_ligand=pl)
+    keep = near_face_mask(ora, b["grid"], sub, geno, pl)
+    assert keep.mean() > 0.9
+    assert_energies_match(np.asarray(energy, np.float32), ref, keep, what=what)
+
+
+def test_config3_full_size_search_sampled(ora, batch3):
+    """Plain search of the whole batch as the benchmark runs it, eagerly and as
+    a captured plan (same bits), checked on a sample against the oracle."""
+    import torch
+    dk, b = batch3["dk"], batch3
+    out = _buffers(N_LIGANDS, b["params"].pop_size, b["stride"])
+    dk.dock_search(b["pocket"], b["L"], b["params"], *out)
+    torch.cuda.synchronize()
+    _check_search_sample(ora, b, out, "config3 plain search", 7)
+    out2 = _buffers(N_LIGANDS, b["params"].pop_size, b["stride"])
+    plan = dk.dock_search_plan_create(b["pocket"], b["L"], b["params"], *out2)
+    dk.dock_search_plan_launch(plan)
+    torch.cuda.synchronize()
+    for x, y in zip(out, out2):
+        assert torch.equal(x, y)
+
+
+def test_config3_full_size_learned_search_sampled(ora, batch3):
+    """The search with proposal rounds (every 5 generations below 100, as the
+    benchmark's learned runs) from a seeded untrained network: every proposal is
+    scored exactly, so the same checks hold."""
+    import torch
+    dk, b = batch3["dk"], batch3
+    from dataclasses import replace
+    net = dk.dock_mlp_create(0, seed=5)
+    p = replace(b["params"], proposal=net, proposal_step=1.0, proposal_every=5, proposal_until=100)
+    out = _buffers(N_LIGANDS, p.pop_size, b["stride"])
+    dk.dock_search(b["pocket"], b["L"], p, *out)
+    torch.cuda.synchronize()
+    _check_search_sample(ora, b, out, "config3 learned search", 8)

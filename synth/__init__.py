@@ -271,6 +271,11 @@ CONFIGS = {
     # from the same size distribution
     4: dict(name="learned proposal vs plain", n_types=12, grid_n=80, n_ligands=5_000, first_id=100_000,
             atoms="lognormal", torsions=(0, 20), pop=150, gens=300, tuples=1_000_000),
+    # validation batch for the learned proposal's round schedule: 2000 more
+    # ligands of the same size law (ids 200000..201999), disjoint from the
+    # training set and from the batch the comparison is reported on
+    5: dict(name="proposal schedule validation", n_types=12, grid_n=80, n_ligands=2_000, first_id=200_000,
+            atoms="lognormal", torsions=(0, 20), pop=150, gens=300),
 }
 
 

@@ -106,9 +106,13 @@ def train(x, t, cfg: TrainConfig):
 
 @dataclass
 class ProposalConfig:
+    """Round schedule of the learned proposal.  The defaults were chosen on a
+    validation batch of 2000 ligands disjoint from the training set and from
+    the batch the comparison is reported on (time to the plain search's final
+    median + 0.1 kcal/mol, over six seeds)."""
     step: float = 1.0     # alpha_max
-    every: int = 5        # learned round every this many generations (0: only after the initial population)
-    until: int = 100      # no later rounds at or after this generation
+    every: int = 12       # learned round every this many generations (0: only after the initial population)
+    until: int = 300      # no later rounds at or after this generation
 
 
 def time_to_target(pocket, ligs, params: dk.SearchParams, stride: int, target, net=None,

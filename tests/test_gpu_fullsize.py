@@ -145,14 +145,16 @@ def test_config3_full_size_search_sampled(ora, batch3):
 
 
 def test_config3_full_size_learned_search_sampled(ora, batch3):
-    """The search with proposal rounds (every 5 generations below 100, as the
-    benchmark's learned runs) from a seeded untrained network: every proposal is
-    scored exactly, so the same checks hold."""
+    """The search with proposal rounds (the benchmark's schedule) from a seeded
+    untrained network: every proposal is scored exactly, so the same checks hold."""
     import torch
     dk, b = batch3["dk"], batch3
     from dataclasses import replace
     net = dk.dock_mlp_create(0, seed=5)
-    p = replace(b["params"], proposal=net, proposal_step=1.0, proposal_every=5, proposal_until=100)
+    from paper_2509_12232_amd import proposal as pr
+    sched = pr.ProposalConfig()
+    p = replace(b["params"], proposal=net, proposal_step=sched.step, proposal_every=sched.every,
+                proposal_until=sched.until)
     out = _buffers(N_LIGANDS, p.pop_size, b["stride"])
     dk.dock_search(b["pocket"], b["L"], p, *out)
     torch.cuda.synchronize()

@@ -62,6 +62,7 @@ struct dock_mlp {
   int device = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr;  // [kMlpParams] each
   bf16 *wt1 = nullptr, *wt2 = nullptr, *wt3 = nullptr, *wr2 = nullptr, *wr3 = nullptr;
+  bf16 *wf = nullptr;  // forward weights in fragment order (the fused proposal kernel)
   int64_t adam_t = 0;
   // training workspace for up to ws_rows rows
   char *ws = nullptr;
@@ -69,7 +70,7 @@ struct dock_mlp {
   MlpActs A{};
   MlpGrads G{};
   float *tb = nullptr, *wb = nullptr;  // gathered targets [rows][32] and weights [rows]
-  MlpWeights weights() const { return MlpWeights{master, wt1, wt2, wt3, wr2, wr3}; }
+  MlpWeights weights() const { return MlpWeights{master, wt1, wt2, wt3, wr2, wr3, wf}; }
   hipError_t ensure_workspace(int64_t mp) {
     if (mp <= ws_rows) return hipSuccess;
     if (ws) {
@@ -100,7 +101,7 @@ struct dock_mlp {
 
 static void free_mlp(dock_mlp *n) {
   for (void *p : {(void *)n->master, (void *)n->m, (void *)n->v, (void *)n->wt1, (void *)n->wt2, (void *)n->wt3,
-                  (void *)n->wr2, (void *)n->wr3, (void *)n->ws})
+                  (void *)n->wr2, (void *)n->wr3, (void *)n->wf, (void *)n->ws})
     if (p) (void)hipFree(p);
   delete n;
 }
@@ -133,7 +134,7 @@ static hipError_t load_params(dock_mlp *n, const float *host) {
   hipError_t e = hipMemcpy(n->master, host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(n->m, 0, sizeof(float) * kMlpParams);
   if (e == hipSuccess) e = hipMemset(n->v, 0, sizeof(float) * kMlpParams);
-  if (e == hipSuccess) e = launch_mlp_refresh(n->master, n->wt1, n->wt2, n->wt3, n->wr2, n->wr3, nullptr);
+  if (e == hipSuccess) e = launch_mlp_refresh(n->master, n->wt1, n->wt2, n->wt3, n->wr2, n->wr3, n->wf, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   n->adam_t = 0;
   return e;
@@ -154,6 +155,7 @@ extern "C" dock_status dock_mlp_create(int32_t device, uint64_t seed, dock_mlp *
   if (e == hipSuccess) e = hipMalloc((void **)&n->wt3, sizeof(bf16) * kMlpHidden * kMlpOut);
   if (e == hipSuccess) e = hipMalloc((void **)&n->wr2, sizeof(bf16) * kMlpHidden * kMlpHidden);
   if (e == hipSuccess) e = hipMalloc((void **)&n->wr3, sizeof(bf16) * kMlpHidden * kMlpOut);
+  if (e == hipSuccess) e = hipMalloc((void **)&n->wf, sizeof(bf16) * kFragTotal);
   if (e == hipSuccess) e = load_params(n, initial_params(seed).data());
   if (e != hipSuccess) {
     free_mlp(n);
@@ -289,7 +291,7 @@ extern "C" dock_status dock_mlp_train(dock_mlp *n, const float *x, const float *
     n->adam_t += 1;
     AdamStep a{lr, 0.9f, 0.999f, 1e-8f, (float)(1.0 - pow(0.9, (double)n->adam_t)),
                (float)(1.0 - pow(0.999, (double)n->adam_t))};
-    HIP_TRY(launch_mlp_adam(n->master, n->m, n->v, n->G.grads, a, n->wt1, n->wt2, n->wt3, n->wr2, n->wr3, s), "adam");
+    HIP_TRY(launch_mlp_adam(n->master, n->m, n->v, n->G.grads, a, n->wt1, n->wt2, n->wt3, n->wr2, n->wr3, n->wf, s), "adam");
   }
   return DOCK_OK;
 }

@@ -32,7 +32,17 @@ struct MlpWeights {
   const float *master;  // packed fp32 parameters (biases are read from here)
   const bf16 *wt1, *wt2, *wt3;
   const bf16 *wr2, *wr3;
+  const bf16 *wf;       // the three forward weights in MFMA fragment order (kFragW1/2/3)
 };
+
+// Fragment order of a forward weight Bt[N][K] (Bt[n][k] = W[k][n]): for output
+// tile t (columns 32 t ..) and reduction step s (k = 16 s ..), the 64 lanes'
+// B fragments, lane l holding Bt[32 t + l % 32][16 s + 8 (l / 32) + 0..7], are
+// 1 KB contiguous, so a wavefront loads a fragment as whole cache lines.
+constexpr int kFragW1 = 0;
+constexpr int kFragW2 = kFragW1 + kMlpIn * kMlpHidden;
+constexpr int kFragW3 = kFragW2 + kMlpHidden * kMlpHidden;
+constexpr int kFragTotal = kFragW3 + kMlpHidden * kMlpOut;
 
 // Activation buffers of one batch of rows (mp = rows rounded up to 32).  "p8"
 // copies hold eight consecutive rows interleaved, element (r, c) at
@@ -73,9 +83,9 @@ struct AdamStep {
   float c1, c2;  // 1 - beta1^t, 1 - beta2^t
 };
 hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grads, const AdamStep &a, bf16 *wt1,
-                           bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, hipStream_t s);
+                           bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, bf16 *wf, hipStream_t s);
 // bfloat16 copies from the packed parameters.
-hipError_t launch_mlp_refresh(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3,
+hipError_t launch_mlp_refresh(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, bf16 *wf,
                               hipStream_t s);
 
 // Genotype rows of a population [n_ligs][pop][g_stride] (row r = ligand r / pop).

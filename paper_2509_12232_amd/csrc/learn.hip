@@ -206,34 +206,44 @@ __global__ __launch_bounds__(256) void ordered_sum_kernel(const float *part, int
   if (threadIdx.x == 0) out[0] = sh[0] * scale;
 }
 
+// Position of Bt[n][k] of a [N][K] forward weight in fragment order.
+__device__ __forceinline__ int frag_index(int n, int k, int K) {
+  const int t = n >> 5, c = n & 31, s = k >> 4, kk = k & 15;
+  return (((t * (K >> 4) + s) * kWave + c + 32 * (kk >> 3)) << 3) + (kk & 7);
+}
+
 // bfloat16 copies of weight element e of the packed vector (e < kOffW3 + 256 * 32,
 // biases excluded by the caller).
 __device__ __forceinline__ void store_weight_copies(int e, float v, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2,
-                                                    bf16 *wr3) {
+                                                    bf16 *wr3, bf16 *wf) {
   const bf16 h = (bf16)v;
   if (e < kOffB1) {
     const int k = e / kMlpHidden, n = e % kMlpHidden;
     wt1[n * kMlpIn + k] = h;
+    wf[kFragW1 + frag_index(n, k, kMlpIn)] = h;
   } else if (e >= kOffW2 && e < kOffB2) {
     const int o = e - kOffW2, k = o / kMlpHidden, n = o % kMlpHidden;
     wt2[n * kMlpHidden + k] = h;
     wr2[k * kMlpHidden + n] = h;
+    wf[kFragW2 + frag_index(n, k, kMlpHidden)] = h;
   } else if (e >= kOffW3 && e < kOffB3) {
     const int o = e - kOffW3, k = o / kMlpOut, n = o % kMlpOut;
     wt3[n * kMlpHidden + k] = h;
     wr3[k * kMlpOut + n] = h;
+    wf[kFragW3 + frag_index(n, k, kMlpHidden)] = h;
   }
 }
 
-__global__ void mlp_refresh_kernel(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3) {
+__global__ void mlp_refresh_kernel(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3,
+                                   bf16 *wf) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kMlpParams) return;
-  store_weight_copies(e, master[e], wt1, wt2, wt3, wr2, wr3);
+  store_weight_copies(e, master[e], wt1, wt2, wt3, wr2, wr3, wf);
 }
 
 // Adam (Kingma & Ba, ICLR 2015) with bias correction c1 = 1 - beta1^t, c2 = 1 - beta2^t.
 __global__ void mlp_adam_kernel(float *p, float *m, float *v, const float *grads, AdamStep a, bf16 *wt1, bf16 *wt2,
-                                bf16 *wt3, bf16 *wr2, bf16 *wr3) {
+                                bf16 *wt3, bf16 *wr2, bf16 *wr3, bf16 *wf) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kMlpParams) return;
   const float g = grads[e];
@@ -243,7 +253,7 @@ __global__ void mlp_adam_kernel(float *p, float *m, float *v, const float *grads
   v[e] = vv;
   const float w = p[e] - a.lr * (mm / a.c1) / (sqrtf(vv / a.c2) + a.eps);
   p[e] = w;
-  store_weight_copies(e, w, wt1, wt2, wt3, wr2, wr3);
+  store_weight_copies(e, w, wt1, wt2, wt3, wr2, wr3, wf);
 }
 
 // ------------------------------------------------------------------ genotypes
@@ -343,7 +353,21 @@ __device__ void decode_row(const PopRows &R, int64_t r, const float *genotypes, 
   float *o = prop + r * R.g_stride;
   DrawStream s(seed, (uint64_t)ind, (uint64_t)generation, (uint64_t)lig, kPurposeProposal);
   const float alpha = alpha_max * (float)(1.0 - s.unit());
-  for (int j = 0; j < R.g_stride; ++j) o[j] = g[j];
+  // the row copied as is first (genes past the encoded torsions keep their
+  // values), in blocks whose loads are issued before their stores
+  {
+    const float *__restrict__ src = g;
+    float *__restrict__ dst = o;
+    const int G = R.g_stride;
+    for (int j0 = 0; j0 < G; j0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = src[min(j0 + i, G - 1)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (j0 + i < G) dst[j0 + i] = v[i];
+    }
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     float c, h;
@@ -359,46 +383,64 @@ __device__ void decode_row(const PopRows &R, int64_t r, const float *genotypes, 
 }
 
 // ---------------------------------------------------- fused proposal kernel
-// One wavefront (the whole workgroup) takes 32 population rows through encode,
+// One wavefront takes 32 population rows through encode,
 // the three layers and decode.  The rows' activations stay in LDS, one padded
 // row per individual (the padding puts consecutive rows' 16-byte fragments in
-// different banks); weight fragments stream from L2, where every wavefront
-// reads the same 196 KB.  The products run in the same k order as the
-// per-layer kernels, so the network output is the same to the bit.
-constexpr int kPropRows = 32;
+// different banks); weight fragments stream from L2 in fragment order (each a
+// contiguous 1 KB), where every wavefront reads the same 196 KB.  The products
+// run in the same k order as the per-layer kernels, so the network output is
+// the same to the bit.
+constexpr int kPropWaves = 4;                     // wavefronts of a workgroup
+constexpr int kPropRows = 32 * kPropWaves;        // rows of a workgroup, 32 per wavefront
 constexpr int kHStride = kMlpHidden + 8;  // bfloat16 per LDS row
 
 __device__ __forceinline__ bf16x8 lds_frag(const bf16 *h, int l, int k0) {
   return *reinterpret_cast<const bf16x8 *>(h + (l & 31) * kHStride + k0 + 8 * (l >> 5));
 }
 
-// acc[t] += h[rows][0..K) * W (Bt = [32 * NT][K]) for NT column tiles of 32
+// acc[t] = h[rows][0..K) * W for NT column tiles of 32, W given in fragment
+// order (Bf: the layer's fragments, tile-major, K / 16 steps per tile)
 template <int NT, int K>
-__device__ __forceinline__ void layer_product(const bf16 *h, const bf16 *Bt, int l, f32x16 acc[NT]) {
+__device__ __forceinline__ void layer_product(const bf16 *h, const bf16 *Bf, int l, f32x16 acc[NT]) {
+  constexpr int KS = K / 16;
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
-  const bf16 *b = Bt + (l & 31) * K + 8 * (l >> 5);
-  for (int k = 0; k < K; k += 16) {
-    const bf16x8 a = lds_frag(h, l, k);
+  const bf16 *b = Bf + 8 * l;
+  for (int s = 0; s < KS; ++s) {
+    const bf16x8 a = lds_frag(h, l, 16 * s);
     bf16x8 bt[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) bt[t] = frag(b + t * 32 * K + k);
+    for (int t = 0; t < NT; ++t) bt[t] = frag(b + (t * KS + s) * 8 * kWave);
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = mfma(a, bt[t], acc[t]);
   }
 }
 
-// h[rows][col] = bfloat16(relu(acc + bias[col]))
+__device__ __forceinline__ uint32_t bf16_bits(float v) { return __builtin_bit_cast(unsigned short, (bf16)v); }
+
+// h[rows][col] = bfloat16(relu(acc + bias[col])), written as bfloat16 pairs.
+// Tiles go two at a time: lanes l and l ^ 1 hold columns 2c and 2c + 1 of both
+// tiles; the even lane writes the pair of the first tile and the odd lane the
+// pair of the second, after swapping one value, so each 32-bit store of 32
+// lanes covers 32 consecutive words of one row (no bank conflict).
 template <int NT>
 __device__ __forceinline__ void store_hidden(bf16 *h, const float *bias, int l, const f32x16 acc[NT]) {
+  static_assert(NT % 2 == 0, "tiles in pairs");
+  const bool odd = l & 1;
+  const int c = l & 31;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = t * 32 + (l & 31);
-    const float b = bias[col];
+  for (int t = 0; t < NT; t += 2) {
+    const float b0 = bias[t * 32 + c], b1 = bias[(t + 1) * 32 + c];
+    const int col = (odd ? (t + 1) * 32 : t * 32) + (c & ~1);   // first column of the pair this lane writes
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const float v = acc[t][r] + b;
-      h[acc_row(r, l) * kHStride + col] = (bf16)(v > 0.f ? v : 0.f);
+      const float v0 = acc[t][r] + b0, v1 = acc[t + 1][r] + b1;
+      const uint32_t a = bf16_bits(v0 > 0.f ? v0 : 0.f), bb = bf16_bits(v1 > 0.f ? v1 : 0.f);
+      // the even lane sends its second-tile value, the odd lane its first-tile
+      // value; quad_perm [1, 0, 3, 2] gives each lane the value of lane l ^ 1
+      const uint32_t nb = (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? a : bb), 0xB1, 0xF, 0xF, false);
+      const uint32_t pair = odd ? (nb | (bb << 16)) : (a | (nb << 16));
+      *reinterpret_cast<uint32_t *>(h + acc_row(r, l) * kHStride + col) = pair;
     }
   }
 }
@@ -413,12 +455,16 @@ struct ProposeLaunch {
   int32_t generation;
 };
 
-__global__ __launch_bounds__(64) void propose_kernel(ProposeLaunch P) {
-  __shared__ __attribute__((aligned(16))) bf16 h[kPropRows * kHStride];
-  const int l = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * kPropRows;
+// A workgroup of kPropWaves wavefronts, 32 rows each, walks the layers in step
+// (the barriers between phases), so the wavefronts of a workgroup load the same
+// weight fragments at about the same time and all but the first find them in L1.
+__global__ __launch_bounds__(64 * kPropWaves) void propose_kernel(ProposeLaunch P) {
+  __shared__ __attribute__((aligned(16))) bf16 h_all[kPropRows * kHStride];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bf16 *h = h_all + w * 32 * kHStride;             // this wavefront's 32 rows
+  const int64_t row0 = (int64_t)blockIdx.x * kPropRows + 32 * w;
   const int64_t r = row0 + (l & 31);
-  const bool mine = l < kPropRows;  // lanes 0..31 encode and decode one row each
+  const bool mine = l < 32;  // lanes 0..31 encode and decode one row each
   if (mine) {
     float f[kMlpIn];
     if (r < P.R.n_rows) {
@@ -426,32 +472,41 @@ __global__ __launch_bounds__(64) void propose_kernel(ProposeLaunch P) {
     } else {
       for (int j = 0; j < kMlpIn; ++j) f[j] = 0.f;
     }
-    for (int j = 0; j < kMlpIn; ++j) h[l * kHStride + j] = (bf16)f[j];
+    // the row as twelve 16-byte stores
+#pragma unroll
+    for (int j = 0; j < kMlpIn; j += 8) {
+      bf16x8 v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (bf16)f[j + i];
+      *reinterpret_cast<bf16x8 *>(h + l * kHStride + j) = v;
+    }
   }
   __syncthreads();
   f32x16 acc[kMlpHidden / 32];
-  layer_product<kMlpHidden / 32, kMlpIn>(h, P.W.wt1, l, acc);
+  layer_product<kMlpHidden / 32, kMlpIn>(h, P.W.wf + kFragW1, l, acc);
   __syncthreads();
   store_hidden<kMlpHidden / 32>(h, P.W.master + kOffB1, l, acc);
   __syncthreads();
-  layer_product<kMlpHidden / 32, kMlpHidden>(h, P.W.wt2, l, acc);
+  layer_product<kMlpHidden / 32, kMlpHidden>(h, P.W.wf + kFragW2, l, acc);
   __syncthreads();
   store_hidden<kMlpHidden / 32>(h, P.W.master + kOffB2, l, acc);
   __syncthreads();
   f32x16 out[1];
-  layer_product<1, kMlpHidden>(h, P.W.wt3, l, out);
+  layer_product<1, kMlpHidden>(h, P.W.wf + kFragW3, l, out);
   __syncthreads();
-  // network outputs as float32 rows of 32 in the same LDS
+  // network outputs as float32 rows in the wavefront's LDS rows, padded to 33
+  // floats so that the lanes reading their own rows hit different banks
+  constexpr int kYStride = kMlpOut + 1;
   float *y = reinterpret_cast<float *>(h);
   {
     const int col = l & 31;
     const float b = P.W.master[kOffB3 + col];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) y[acc_row(i, l) * kMlpOut + col] = out[0][i] + b;
+    for (int i = 0; i < 16; ++i) y[acc_row(i, l) * kYStride + col] = out[0][i] + b;
   }
   __syncthreads();
   if (mine && r < P.R.n_rows)
-    decode_row(P.R, r, P.genotypes, y + l * kMlpOut, P.alpha_max, P.seed, P.generation, P.proposals);
+    decode_row(P.R, r, P.genotypes, y + l * kYStride, P.alpha_max, P.seed, P.generation, P.proposals);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -554,16 +609,16 @@ hipError_t launch_mlp_backward(const MlpWeights &W, const MlpActs &A, const MlpG
 }
 
 hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grads, const AdamStep &a, bf16 *wt1,
-                           bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, hipStream_t s) {
+                           bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, bf16 *wf, hipStream_t s) {
   hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, master, m, v, grads, a,
-                     wt1, wt2, wt3, wr2, wr3);
+                     wt1, wt2, wt3, wr2, wr3, wf);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_refresh(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3,
+hipError_t launch_mlp_refresh(const float *master, bf16 *wt1, bf16 *wt2, bf16 *wt3, bf16 *wr2, bf16 *wr3, bf16 *wf,
                               hipStream_t s) {
   hipLaunchKernelGGL(mlp_refresh_kernel, dim3(blocks_for(kMlpParams, 256)), dim3(256), 0, s, master, wt1, wt2, wt3,
-                     wr2, wr3);
+                     wr2, wr3, wf);
   return hipGetLastError();
 }
 
@@ -586,7 +641,7 @@ hipError_t launch_propose(const PopRows &R, const MlpWeights &W, const float *ge
                           uint64_t seed, int32_t generation, float *proposals, hipStream_t s) {
   if (R.n_rows <= 0) return hipSuccess;
   ProposeLaunch P{R, W, genotypes, proposals, alpha_max, seed, generation};
-  hipLaunchKernelGGL(propose_kernel, dim3(blocks_for(R.n_rows, kPropRows)), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(propose_kernel, dim3(blocks_for(R.n_rows, kPropRows)), dim3(64 * kPropWaves), 0, s, P);
   return hipGetLastError();
 }
 

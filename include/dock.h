@@ -290,7 +290,10 @@ typedef struct {
   int32_t waves_per_group;  /* 0..4 */
 } dock_search_shape;
 
-/* Current shapes, host dock_search_shape[DOCK_SEARCH_BUCKETS]. */
+/* The handle's shapes, host dock_search_shape[DOCK_SEARCH_BUCKETS]: the
+ * defaults, the ones set below, or the ones the autotuner fixed (timed or found
+ * in its cache).  A search of a bucket whose shape is not fixed uses a cached
+ * shape for its pocket and population size if there is one. */
 dock_status dock_search_shapes(const dock_ligands *ligs, dock_search_shape *shapes);
 /* Fixes the shapes (host array as above; max_atoms must match). */
 dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *shapes);
@@ -298,12 +301,26 @@ dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *
  * generations (params' pop_size, seed, box) of the bucket's ligands for every
  * shape (1, 2 and 4 lanes per pose x 1 up to 4 wavefronts), warm-up run first,
  * with HIP events on stream, and fixes the fastest.  Results are cached for the
- * process under (device, map layout and dimensions, bucket, its largest ligand,
- * pop_size); a cached bucket is not timed again, and dock_search uses cached
- * shapes for handles whose shapes were not fixed.  Synchronous; allocates and
- * frees its own scratch state; 1 <= tune_generations <= 1000. */
+ * process under (device architecture and compute-unit count, map layout and
+ * dimensions, bucket, its largest ligand, pop_size); a cached bucket is not
+ * timed again, and dock_search uses cached shapes for handles whose shapes were
+ * not fixed.  Synchronous; allocates and frees its own scratch state;
+ * 1 <= tune_generations <= 1000. */
 dock_status dock_search_autotune(const dock_pocket *pocket, dock_ligands *ligs, const dock_search_params *params,
                                  int32_t g_stride, int32_t tune_generations, void *stream);
+
+/* The autotuner's cache as a file, so that a later process (on a device of the
+ * same architecture and compute-unit count) uses tuned shapes without timing
+ * them again.  dock_search_tune_save writes every cached shape of this process
+ * to the text file at path (a header line, then one line per shape: arch n_cu
+ * layout nx ny nz n_types bucket_upper largest_ligand pop lanes_per_pose
+ * waves_per_group), replacing the file.  dock_search_tune_load reads such a
+ * file and merges it into this process's cache (an entry with the same key is
+ * replaced); if any line is malformed or out of range nothing is loaded.
+ * Host-only; no device is touched.  Errors: DOCK_E_INVALID (null path, the
+ * file cannot be written or read, a malformed line). */
+dock_status dock_search_tune_save(const char *path);
+dock_status dock_search_tune_load(const char *path);
 
 /* ---- Learned proposal --------------------------------------------------------
  * An addition to the paper's method (whose search, Sec. V, has no learned

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <numeric>
 #include <vector>
@@ -159,7 +160,13 @@ static void fill_pocket_ff(dock_pocket *p, const dock_forcefield *ff) {
 static hipError_t fill_device_info(dock_pocket *p) {
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, p->device);
-  if (e == hipSuccess) p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  if (e == hipSuccess) {
+    p->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    // the architecture name without its feature suffixes (gfx950:sramecc+:xnack- -> gfx950)
+    std::string arch(prop.gcnArchName);
+    p->arch = arch.substr(0, arch.find(':'));
+    if (p->arch.empty()) p->arch = "unknown";
+  }
   return e;
 }
 
@@ -707,21 +714,28 @@ extern "C" dock_status dock_de_trials(const dock_ligands *L, const dock_search_p
 namespace {
 
 // Launch shapes found by the autotuner, for the whole process, keyed by what
-// decides them: device, map layout and size, the bucket and its largest ligand,
-// the population size.
+// decides them: the kind of device (architecture and compute units), map layout
+// and size, the bucket and its largest ligand, the population size.  The key
+// names no device index, so shapes saved to a file apply to any device of the
+// same kind.
 struct ShapeKey {
-  int device, layout, nx, ny, nz, n_types, upper, lds_atoms, pop;
+  std::string arch;
+  int n_cu, layout, nx, ny, nz, n_types, upper, lds_atoms, pop;
   bool operator<(const ShapeKey &o) const {
-    return std::tie(device, layout, nx, ny, nz, n_types, upper, lds_atoms, pop) <
-           std::tie(o.device, o.layout, o.nx, o.ny, o.nz, o.n_types, o.upper, o.lds_atoms, o.pop);
+    return std::tie(arch, n_cu, layout, nx, ny, nz, n_types, upper, lds_atoms, pop) <
+           std::tie(o.arch, o.n_cu, o.layout, o.nx, o.ny, o.nz, o.n_types, o.upper, o.lds_atoms, o.pop);
   }
 };
 std::mutex g_shape_mu;
 std::map<ShapeKey, SearchShape> g_shapes;
 
 ShapeKey shape_key(const dock_pocket *p, const LigandBucket &B, int pop) {
-  return ShapeKey{p->device, p->layout, p->geom.nx, p->geom.ny, p->geom.nz, p->geom.n_types, B.upper, B.lds_atoms, pop};
+  return ShapeKey{p->arch, p->n_cu, p->layout, p->geom.nx, p->geom.ny, p->geom.nz, p->geom.n_types,
+                  B.upper, B.lds_atoms, pop};
 }
+
+constexpr const char *kTuneHeader = "# dock search shapes v1: arch n_cu layout nx ny nz n_types bucket_upper "
+                                    "largest_ligand pop lanes_per_pose waves_per_group";
 
 }  // namespace
 
@@ -1110,6 +1124,65 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
   if (queue) (void)hipFree(queue);
   if (buf) (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(e, step);
+  return DOCK_OK;
+}
+
+// The autotuner's cache as a text file: a header line, then one shape per line.
+extern "C" dock_status dock_search_tune_save(const char *path) {
+  if (!path) return set_err(DOCK_E_INVALID, "null path");
+  std::string text = std::string(kTuneHeader) + "\n";
+  {
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    char line[256];
+    for (const auto &kv : g_shapes) {
+      const ShapeKey &k = kv.first;
+      snprintf(line, sizeof line, "%s %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.n_cu, k.layout, k.nx,
+               k.ny, k.nz, k.n_types, k.upper, k.lds_atoms, k.pop, kv.second.lanes_per_pose, kv.second.waves);
+      text += line;
+    }
+  }
+  FILE *f = fopen(path, "w");
+  if (!f) return set_err(DOCK_E_INVALID, "cannot write %s", path);
+  const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return set_err(DOCK_E_INVALID, "cannot write %s", path);
+  return DOCK_OK;
+}
+
+extern "C" dock_status dock_search_tune_load(const char *path) {
+  if (!path) return set_err(DOCK_E_INVALID, "null path");
+  FILE *f = fopen(path, "r");
+  if (!f) return set_err(DOCK_E_INVALID, "cannot read %s", path);
+  std::vector<std::pair<ShapeKey, SearchShape>> entries;
+  char line[512];
+  int n_line = 0;
+  dock_status st = DOCK_OK;
+  while (fgets(line, sizeof line, f)) {
+    ++n_line;
+    if (line[0] == '#' || line[0] == '\n' || line[0] == '\0') continue;
+    char arch[64];
+    ShapeKey k{};
+    SearchShape sh{};
+    char extra[2];
+    const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %1s", arch, &k.n_cu, &k.layout, &k.nx, &k.ny,
+                           &k.nz, &k.n_types, &k.upper, &k.lds_atoms, &k.pop, &sh.lanes_per_pose, &sh.waves, extra);
+    const bool valid = got == 12 && k.n_cu > 0 && k.layout >= kLinear && k.layout <= kQuadLine && k.nx >= 2 &&
+                       k.ny >= 2 && k.nz >= 2 && k.n_types >= 1 && k.n_types <= kMaxTypes && k.upper >= 1 &&
+                       k.upper <= kMaxAtoms && k.lds_atoms >= 1 && k.lds_atoms <= k.upper && k.pop >= 4 &&
+                       (sh.lanes_per_pose == 1 || sh.lanes_per_pose == 2 || sh.lanes_per_pose == 4) &&
+                       sh.waves >= 0 && sh.waves <= kSearchMaxThreads / kWave;
+    if (!valid) {
+      st = set_err(DOCK_E_INVALID, "%s line %d: not a search shape", path, n_line);
+      break;
+    }
+    k.arch = arch;
+    entries.emplace_back(k, sh);
+  }
+  if (st == DOCK_OK && ferror(f)) st = set_err(DOCK_E_INVALID, "cannot read %s", path);
+  fclose(f);
+  if (st) return st;
+  std::lock_guard<std::mutex> g(g_shape_mu);
+  for (const auto &kv : entries) g_shapes[kv.first] = kv.second;
   return DOCK_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <stdarg.h>
 
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "dock.h"
@@ -59,6 +60,7 @@ struct dock_pocket {
   int64_t plane = 0;
   int32_t layout = dock::kLinear;    // layout the scoring kernel reads
   int32_t n_cu = 1;            // compute units of the device (persistent launch size)
+  std::string arch;            // device architecture name (keys the autotuner's cache)
   void *tpack = nullptr;       // packed type maps (kQuadLine: all maps)
   float4 *edpack = nullptr;    // packed electrostatic/desolvation records
   int64_t t_stride = 0;

@@ -89,6 +89,8 @@ _SIGS = {
     "dock_search_shapes": [_P, _P],
     "dock_search_set_shapes": [_P, _P],
     "dock_search_autotune": [_P, _P, _P, C.c_int32, C.c_int32, _P],
+    "dock_search_tune_save": [C.c_char_p],
+    "dock_search_tune_load": [C.c_char_p],
     "dock_mlp_create": [C.c_int32, C.c_uint64, _P],
     "dock_mlp_destroy": [_P],
     "dock_mlp_set_params": [_P, _P],
@@ -386,6 +388,16 @@ def dock_search_shapes(ligs: Ligands):
 def dock_search_set_shapes(ligs: Ligands, shapes):
     arr = (_Shape * DOCK_SEARCH_BUCKETS)(*[_Shape(*x) for x in shapes])
     _check(_lib.dock_search_set_shapes(ligs.handle, arr))
+
+
+def dock_search_tune_save(path):
+    """Write the autotuner's cached shapes (this process) to a text file."""
+    _check(_lib.dock_search_tune_save(os.fsencode(path)))
+
+
+def dock_search_tune_load(path):
+    """Merge shapes saved by dock_search_tune_save into this process's cache."""
+    _check(_lib.dock_search_tune_load(os.fsencode(path)))
 
 
 def dock_search_autotune(pocket: Pocket, ligs: Ligands, params: SearchParams, g_stride: int,

@@ -70,3 +70,39 @@ def test_search_params_layout_matches_binding(tmp_path):
     for f in fields:
         assert int(out[f]) == getattr(dock._Params, f).offset, f
     assert int(out["sizeof"]) == ctypes.sizeof(dock._Params)
+
+
+def test_tune_cache_file_roundtrip(tmp_path):
+    """The autotuner's cache file (host-only calls): a saved file loads back to
+    the same entries, and a malformed or out-of-range line loads nothing."""
+    from paper_2509_12232_amd import dock
+    good = tmp_path / "shapes.txt"
+    rows = ["gfx950 256 3 80 80 80 12 32 32 150 2 1", "gfx950 256 3 80 80 80 12 96 96 150 4 4",
+            "gfx942 304 2 64 64 64 8 48 47 128 1 3"]
+    good.write_text("# a comment\n" + "\n".join(rows) + "\n")
+    dock.dock_search_tune_load(good)
+    out = tmp_path / "out.txt"
+    dock.dock_search_tune_save(out)
+    lines = out.read_text().splitlines()
+    assert lines[0].startswith("#")
+    assert set(rows) <= set(lines[1:])
+    # the same key again replaces the entry
+    (tmp_path / "upd.txt").write_text("gfx950 256 3 80 80 80 12 32 32 150 4 2\n")
+    dock.dock_search_tune_load(tmp_path / "upd.txt")
+    dock.dock_search_tune_save(out)
+    lines = set(out.read_text().splitlines()[1:])
+    assert "gfx950 256 3 80 80 80 12 32 32 150 4 2" in lines and rows[0] not in lines
+    for bad in ("gfx950 256 3 80 80 80 12 32 32 150 3 1",     # 3 lanes per pose
+                "gfx950 256 3 80 80 80 12 32 40 150 2 1",     # largest ligand above the bucket
+                "gfx950 256 7 80 80 80 12 32 32 150 2 1",     # unknown layout
+                "gfx950 256 3 80 80 80 12 32 32 150 2",       # a field missing
+                "gfx950 256 3 80 80 80 12 32 32 150 2 1 9"):  # a field too many
+        f = tmp_path / "bad.txt"
+        f.write_text("gfx950 256 3 80 80 80 12 96 96 151 4 4\n" + bad + "\n")   # a new key, then the bad line
+        before = out.read_text()
+        with pytest.raises(dock.DockError):
+            dock.dock_search_tune_load(f)
+        dock.dock_search_tune_save(out)
+        assert out.read_text() == before      # nothing of the bad file was loaded
+    with pytest.raises(dock.DockError):
+        dock.dock_search_tune_load(tmp_path / "missing.txt")

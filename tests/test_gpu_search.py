@@ -212,6 +212,62 @@ def test_launch_shape_does_not_change_results(dk):
     assert np.all(reached[0][1] <= ref[3] + 0.1)
 
 
+def test_tune_cache_file_applies_to_new_handles(dk, tmp_path):
+    """Tuned shapes saved to a file name this device's kind, pocket and buckets;
+    loaded back (edited), they are what a new handle for the same ligands uses,
+    and the search gives the same bits."""
+    ff, rec, grid, maps = system(2, grid_n=48)
+    atoms = [12, 20, 31, 40, 47, 60, 85]
+    ligands = [synth.make_ligand(1, 500 + i, n, min(10, n // 4), 8) for i, n in enumerate(atoms)]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    params = _params(dk, lo, hi, pop_size=75, n_generations=4)
+    print("case: tune cache file, 7 ligands, pop 75", flush=True)
+    dk.dock_search_autotune(pocket, ligs, params, stride, tune_generations=2)
+    tuned = {b: (lp, w) for b, lp, w in dk.dock_search_shapes(ligs)}
+    largest = {}
+    for n in atoms:
+        b = min(x for x in tuned if x >= n)
+        largest[b] = max(largest.get(b, 0), n)
+    path = tmp_path / "tune.txt"
+    dk.dock_search_tune_save(path)
+    mine = {}
+    for line in path.read_text().splitlines()[1:]:
+        f = line.split()
+        key = [int(x) for x in f[1:10]]
+        if key[1:6] == [pocket.layout, 48, 48, 48, 8] and key[8] == 75 and largest.get(key[6]) == key[7]:
+            mine[key[6]] = (key[7], int(f[10]), int(f[11]))
+    assert set(mine) == set(largest)
+    for b, (lig_max, lp, w) in mine.items():
+        assert lig_max == largest[b] and (lp, w) == tuned[b]
+    # edit this pocket's lines to other shapes and load them
+    edited, want = [], {}
+    for line in path.read_text().splitlines()[1:]:
+        f = line.split()
+        b = int(f[7])
+        if (b in mine and int(f[2]) == pocket.layout and int(f[3]) == 48 and int(f[9]) == 75
+                and int(f[8]) == largest[b]):
+            lp = {1: 2, 2: 4, 4: 1}[int(f[10])]
+            f[10], f[11] = str(lp), "1"
+            want[b] = (lp, 1)
+        edited.append(" ".join(f))
+    path.write_text("\n".join(edited) + "\n")
+    dk.dock_search_tune_load(path)
+    # a new handle: the autotuner finds every bucket in the cache and fixes the
+    # loaded shapes without timing (timing would not have chosen the edits)
+    ligs2 = dk.dock_create_ligands(pocket, ligands)
+    dk.dock_search_autotune(pocket, ligs2, params, stride, tune_generations=2)
+    for b, lp, w in dk.dock_search_shapes(ligs2):
+        if b in want:
+            assert (lp, w) == want[b]
+    a = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
+    c = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs2, params, len(ligands), stride)[:4]]
+    for x, y in zip(a, c):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
 def test_search_plan_graph_replays(dk):
     """A search captured into a HIP graph gives, on every replay (with eager work
     and synchronisations between the replays), exactly dock_search's result --

@@ -269,7 +269,62 @@ def search_throughput(B, gens: int, pop: int):
     return {"ligands": L.n, "pop": pop, "generations": gens, "seconds": round(dt, 4),
             "graph_seconds": round(graph_dt, 4), "graph_poses_per_s": round(n / graph_dt, 1),
             "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4),
-            "autotune_s": round(tune_s, 2), "shapes": shapes}
+            "autotune_s": round(tune_s, 2), "shapes": shapes, "roofline": search_roofline(B, n / dt, pop, gens)}
+
+
+def search_roofline(B, poses_per_s: float, pop: int, gens: int):
+    """The search's map lookups and pair terms per second (every scored pose does
+    all of its ligand's), against the two probes measured on the same pocket:
+    the gather probe with a ligand of the batch's median size, and the pair
+    probe.  The two fractions are shares of the time each ceiling alone would
+    need; what they leave is DE work, synchronisation and idle lanes."""
+    import torch
+    dk = B["dk"]
+    L = B["handles"][0]
+    ligands = B["sets"][0]
+    atoms = np.array([lg.n_atoms for lg in ligands], dtype=np.float64)
+    pairs = np.array([L.pair_count(i) for i in range(L.n)], dtype=np.float64)
+    per_pose = pop * (gens + 1)
+    secs = L.n * per_pose / poses_per_s
+    lookups_s = atoms.sum() * per_pose / secs
+    pairs_s = pairs.sum() * per_pose / secs
+    med = int(np.argsort(atoms)[len(atoms) // 2])
+    timeit = _event_timer()
+    lanes_max, per = 1 << 21, 128
+    out = torch.empty(lanes_max, dtype=torch.float32, device="cuda")
+    probe = 0.0
+    for in_flight in (2, 4, 8):
+        for lanes in (1 << 19, 1 << 21):
+            o = out[:lanes]
+            ms = timeit(lambda: dk.dock_gather_probe(B["pocket"], L, med, B["lo"], B["hi"], o, per,
+                                                     in_flight=in_flight))
+            probe = max(probe, lanes * per / (ms * 1e-3))
+    lanes, per = 1 << 20, 1024
+    out = torch.empty(lanes, dtype=torch.float32, device="cuda")
+    pair_probe = lanes * per / (timeit(lambda: dk.dock_pair_probe(B["pocket"], out, per)) * 1e-3)
+    return {"lookups_per_s": round(lookups_s, -6), "gather_probe": round(probe, -6),
+            "gather_frac": round(lookups_s / probe, 4), "pair_terms_per_s": round(pairs_s, -6),
+            "pair_probe": round(pair_probe, -6), "pair_frac": round(pairs_s / pair_probe, 4),
+            "probe_ligand_atoms": int(atoms[med])}
+
+
+def _event_timer(reps: int = 5):
+    """Median of `reps` timed calls (HIP events on the current stream), after one untimed call."""
+    import torch
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+    return timeit
 
 
 def learned_vs_plain():

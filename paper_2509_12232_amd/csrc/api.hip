@@ -38,6 +38,37 @@ dock_status hip_err(hipError_t e, const char *what) {
 }
 
 extern "C" const char *dock_last_error(void) { return g_err; }
+
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return e;
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(device);
+    if (it != pools.end()) {
+      pool = it->second;
+    } else {
+      hipMemPoolProps props{};
+      props.allocType = hipMemAllocationTypePinned;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = device;
+      e = hipMemPoolCreate(&pool, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = UINT64_MAX;
+      e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return e;
+      }
+      pools[device] = pool;
+    }
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
 extern "C" int32_t dock_version(void) { return 1; }
 
 // ------------------------------------------------------------------------------ handles
@@ -909,9 +940,9 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   const size_t nf = (size_t)L->n_ligs * q->pop_size * g_stride;
   SearchScratch X;
   const char *step = "search buffers";
-  hipError_t e = hipMallocAsync((void **)&X.trials, sizeof(float) * nf, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&X.work, sizeof(float) * nf, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&X.queues, sizeof(int32_t) * L->buckets.size(), s);
+  hipError_t e = scratch_alloc((void **)&X.trials, sizeof(float) * nf, s);
+  if (e == hipSuccess) e = scratch_alloc((void **)&X.work, sizeof(float) * nf, s);
+  if (e == hipSuccess) e = scratch_alloc((void **)&X.queues, sizeof(int32_t) * L->buckets.size(), s);
   if (e == hipSuccess)
     e = enqueue_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target, gen_reached,
                        X, s, &step);

@@ -15,6 +15,12 @@ dock_status set_err(dock_status st, const char *fmt, ...);
 // Maps a HIP error to DOCK_E_NOMEM / DOCK_E_DEVICE with the failing step's name.
 dock_status hip_err(hipError_t e, const char *what);
 
+// Stream-ordered scratch from the library's own memory pool of the current
+// device.  The pool keeps freed memory (its release threshold is unlimited), so
+// repeated calls reuse their scratch instead of mapping it again; it lives
+// until the process ends.  Free with hipFreeAsync on a stream.
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s);
+
 #define HIP_TRY(expr, what)                  \
   do {                                       \
     hipError_t e_ = (expr);                  \

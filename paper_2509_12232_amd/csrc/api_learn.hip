@@ -202,7 +202,7 @@ static hipError_t infer_rows(const dock_mlp *net, int64_t n, hipStream_t s, Fill
   MlpActs a;
   carve_acts(sizer, chunk, false, a);
   char *buf = nullptr;
-  hipError_t e = hipMallocAsync((void **)&buf, sizer.off, s);
+  hipError_t e = scratch_alloc((void **)&buf, sizer.off, s);
   if (e != hipSuccess) return e;
   Carver c{buf};
   MlpActs A;

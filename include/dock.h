@@ -249,7 +249,11 @@ dock_status dock_de_trials(const dock_ligands *ligs, const dock_search_params *p
  * (device, may be NULL) and gen_reached [n_ligands] (device, may be NULL,
  * in/out): gen_reached records the number of completed generations at which the
  * population best first reached <= target (-1 while not reached; with init = 1
- * it is reset first).  Errors as dock_score_poses plus bad parameters. */
+ * it is reset first).  Scratch (the trials and a gene-major copy of the
+ * population, 2 x n_ligands x pop_size x g_stride floats) comes stream-ordered
+ * from a memory pool the library keeps per device, which holds freed memory for
+ * the next call until the process ends.  Errors as dock_score_poses plus bad
+ * parameters, DOCK_E_NOMEM. */
 dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, const dock_search_params *params,
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);

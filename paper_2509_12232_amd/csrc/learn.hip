@@ -4,11 +4,13 @@
 // back-propagation, Adam) and the kernels that turn genotypes into network
 // inputs and network outputs into proposal genotypes.
 //
-// Every product is one wavefront per 32x32 output tile.  Operands are kept in
-// HBM in layouts where each lane's eight bfloat16 values of a fragment are one
-// 16-byte load: activations row-major (reduction index contiguous) for the
-// forward and error products, and eight-row interleaved ("p8") copies for the
-// weight-gradient products, whose reduction index is the row.
+// Every training product is one wavefront per 32x32 output tile.  Operands are
+// kept in HBM in layouts where each lane's eight bfloat16 values of a fragment
+// are one 16-byte load: activations row-major (reduction index contiguous) for
+// the forward and error products, and eight-row interleaved ("p8") copies for
+// the weight-gradient products, whose reduction index is the row.  The fused
+// proposal kernel reads a further copy of the forward weights in fragment
+// order, where a whole fragment is one contiguous kilobyte.
 #include <math.h>
 
 #include "learn.h"

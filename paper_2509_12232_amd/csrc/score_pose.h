@@ -15,7 +15,6 @@ namespace dock {
 
 __device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-
 // Raw map values of one atom's grid cell, as loaded for the layout, plus what
 // is needed to finish the interpolation later.  v[b] of the combined value is
 // corner (x + (b&1), y + (b>>1 & 1), z + (b>>2 & 1)).

@@ -8,8 +8,9 @@
 // dock_search runs one persistent kernel per ligand-size bucket: each workgroup
 // (up to four wavefronts) takes the next ligand from a work queue (largest
 // first) and runs its whole search -- initial population, then per generation
-// all trials, their scores and the greedy selection -- with one lane per
-// individual, and no other launch or host round trip.
+// all trials, their scores and the greedy selection -- with no other launch or
+// host round trip.  Steps without a pose use one lane per individual; scoring
+// uses LP = 1, 2 or 4 lanes per individual (the same bits for every LP).
 #include <algorithm>
 
 #include "search.h"

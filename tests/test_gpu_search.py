@@ -317,3 +317,39 @@ def test_search_plan_graph_replays(dk):
         torch.cuda.synchronize()
         for x, y in zip(want, buf[:4] + buf[5:]):
             assert np.array_equal(x.view(np.uint32), y.cpu().numpy().view(np.uint32)), rep
+
+
+@pytest.mark.parametrize("pop", [4, 1000])
+def test_search_population_extremes(dk, ora, pop):
+    """The smallest population DE allows (4: every trial draws the three other
+    members) and one far above a workgroup's lanes (1000), on ligands of 10, 40
+    and 90 atoms: stored energies are the oracle's scores of the stored
+    genotypes, the best is the first minimum, and a split-and-resumed search is
+    the same bits as one call."""
+    from tests._systems import assert_energies_match, near_face_mask
+    ff, rec, grid, maps = system(2, grid_n=48)
+    ligands = [synth.make_ligand(3, 600 + i, n, t, 8) for i, (n, t) in enumerate([(10, 2), (40, 10), (90, 15)])]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    print("case: population", pop, flush=True)
+    full = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=pop, n_generations=8), 3, stride)
+    half = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=pop, n_generations=4), 3, stride)
+    rest = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=pop, n_generations=4, init=0,
+                                                     first_generation=4), 3, stride,
+                           population=half[0], pop_energy=half[1])
+    for x, y in zip(full[:4], rest[:4]):
+        assert np.array_equal(x.cpu().numpy().view(np.uint32), y.cpu().numpy().view(np.uint32))
+    pop_np, pe, bg, be = (x.cpu().numpy() for x in full[:4])
+    np.testing.assert_array_equal(be, pe.min(axis=1))
+    np.testing.assert_array_equal(bg, pop_np[np.arange(3), pe.argmin(axis=1)])
+    rng = np.random.default_rng(pop)
+    members = np.sort(rng.choice(pop, min(pop, 48), replace=False))
+    geno = np.concatenate([pop_np[l, members] for l in range(3)])
+    pl = np.repeat(np.arange(3, dtype=np.int32), len(members))
+    ref = ora.score_poses(grid, maps, ff, ligands, geno, pose_ligand=pl)
+    keep = near_face_mask(ora, grid, ligands, geno, pl)
+    assert_energies_match(np.concatenate([pe[l, members] for l in range(3)]), ref, keep)
+    with pytest.raises(dk.DockError):
+        _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=3, n_generations=1), 3, stride)

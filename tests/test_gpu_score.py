@@ -207,3 +207,40 @@ def test_lanes_per_pose_same_bits(dk, ora):
     assert_energies_match(runs[1][sub], e_ref, keep)
     with pytest.raises(dk.DockError):
         dk.dock_score_set_lanes_per_pose(3)
+
+
+def test_max_torsions_and_types(dk, ora):
+    """The limits of the ABI at once: 32 atom types (34 maps) and a ligand with
+    32 torsions (39 genes), for every map layout and lanes-per-pose shape, plus
+    the DE trial of a 39-gene genotype bit for bit against the oracle."""
+    import torch
+    import oracle
+    nt = 32
+    ff = synth.forcefield(nt)
+    rec = synth.make_receptor(5, 400, nt)
+    grid = synth.make_grid(40, nt)
+    maps = oracle.build_maps(ff, rec, grid)
+    lig = synth.make_ligand(1, 700, 70, 32, nt)
+    assert lig.n_torsions == 32
+    lo, hi = synth.pocket_box(grid, half=2.0)
+    g = synth.sample_genotypes(17, 333, 32, 39, lo, hi)
+    e_ref = ora.score_poses(grid, maps, ff, [lig], g)
+    keep = near_face_mask(ora, grid, [lig], g)
+    try:
+        for layout in (0, 1, 2, 3):
+            pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+            ligs = dk.dock_create_ligands(pocket, [lig])
+            for lp in (1, 2, 4):
+                print("case: 32 types, 32 torsions, layout", layout, "lanes", lp, flush=True)
+                dk.dock_score_set_lanes_per_pose(lp)
+                assert_energies_match(_gpu_energies(dk, pocket, ligs, g), e_ref, keep)
+    finally:
+        dk.dock_score_set_lanes_per_pose(0)
+    P = 40
+    params = dict(pop_size=P, n_generations=1, seed=9, box_lo=tuple(lo), box_hi=tuple(hi))
+    pop = ora.de_init(lig, ora.SearchParams(**params), 0, 39)[None]
+    tr = torch.zeros((1, P, 39), dtype=torch.float32, device="cuda")
+    dk.dock_de_trials(ligs, dk.SearchParams(**params), 4, torch.from_numpy(pop).cuda(), tr)
+    torch.cuda.synchronize()
+    ref = ora.de_trials(lig, ora.SearchParams(**params), 0, 4, pop[0])
+    assert np.array_equal(tr.cpu().numpy()[0].view(np.uint32), ref.view(np.uint32))

@@ -407,6 +407,50 @@ def learned_vs_plain():
     }
 
 
+def schedule_sweep(seeds=(1, 2)):
+    """Chooses the learned proposal's round schedule on the validation batch
+    (2000 ligands disjoint from the training set and from the batch the
+    comparison is reported on): the network is trained as in learned_vs_plain,
+    then every schedule of a grid is run from a fresh population and timed to
+    the plain search's final median + 0.1 kcal/mol on the same seed.  Prints one
+    JSON line per (schedule, seed) and the ranking by mean speedup."""
+    import torch
+    from dataclasses import replace
+    from paper_2509_12232_amd import proposal as pr
+    B = batch_setup(5, extra_cfg=4)
+    dk = B["dk"]
+    L_val, L_tr = B["handles"]
+    stride = B["stride"]
+    c4 = synth.CONFIGS[4]
+    P = dk.SearchParams(pop_size=c4["pop"], n_generations=c4["gens"], seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    for L in (L_val, L_tr):
+        dk.dock_search_autotune(B["pocket"], L, P, stride, tune_generations=3)
+    snaps, fin = pr.plain_snapshots(B["pocket"], L_tr, P, stride, pr.SNAPSHOT_GENERATIONS)
+    x, t = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
+    del snaps
+    net, _ = pr.train(x, t, pr.TrainConfig(n_tuples=c4["tuples"]))
+    del x, t
+    torch.cuda.synchronize()
+    grid = [(a, e, u) for a in (0.5, 1.0, 1.5) for e in (3, 5, 8, 12) for u in (50, 100, 150, 300)]
+    speed = {k: [] for k in grid}
+    for seed in seeds:
+        Ps = replace(P, seed=seed)
+        pts, buf = pr.anytime(B["pocket"], L_val, Ps, stride)
+        level = float(np.median(buf["be"].cpu().numpy())) + 0.1
+        t_plain, _ = pr.time_to_level(pts, level)
+        for a, e, u in grid:
+            lp, _ = pr.anytime(B["pocket"], L_val, Ps, stride, net, pr.ProposalConfig(a, e, u))
+            t_l, g_l = pr.time_to_level(lp, level)
+            sp = t_plain / t_l if t_l else 0.0
+            speed[(a, e, u)].append(sp)
+            print(json.dumps({"seed": seed, "alpha_max": a, "every": e, "until": u,
+                              "ms": None if t_l is None else round(t_l, 1), "plain_ms": round(t_plain, 1),
+                              "speedup": round(sp, 3)}), flush=True)
+    rank = sorted(speed.items(), key=lambda kv: -float(np.mean(kv[1])))
+    print(json.dumps({"ranking": [{"alpha_max": a, "every": e, "until": u, "mean_speedup": round(float(np.mean(v)), 3)}
+                                  for (a, e, u), v in rank[:10]]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +463,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: one 1 GiB device copy (calibration of the "
                          "FETCH_SIZE/WRITE_SIZE counters) and two scoring steps, nothing else")
+    ap.add_argument("--schedule-sweep", action="store_true",
+                    help="choose the learned proposal's round schedule on the validation batch, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the scoring workload would shard by "
@@ -428,6 +474,9 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.schedule_sweep:
+        schedule_sweep()
+        return
     S = setup(args.poses)
     dk = S["dk"]
     stream = torch.cuda.current_stream()

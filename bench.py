@@ -523,6 +523,9 @@ def main():
     traffic = recorded_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gather_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                # the measured line traffic as a rate: what the fabric actually moves
+                "traffic_GBs": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
+                "traffic_frac": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
                 "lanes_per_pose": S["dk"].dock_score_lanes_per_pose(S["ligs"]),
                 "kernel_ms_sd": round(float(np.std(step_ms)), 4), "kernel_ms_min": round(float(np.min(step_ms)), 4),

@@ -353,3 +353,37 @@ def test_search_population_extremes(dk, ora, pop):
     assert_energies_match(np.concatenate([pe[l, members] for l in range(3)]), ref, keep)
     with pytest.raises(dk.DockError):
         _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=3, n_generations=1), 3, stride)
+
+
+def test_handles_release_device_memory(dk):
+    """Pockets (with their quad-line copy), ligand sets (with side streams),
+    search plans and networks give back their device memory when destroyed:
+    twenty create/use/destroy cycles leave free memory where one cycle left it."""
+    import gc
+    import torch
+    ff, rec, grid, maps = system(2, grid_n=48)
+    ligands = [synth.make_ligand(1, 800 + i, n, 5, 8) for i, n in enumerate([14, 30, 50])]
+    lo, hi = synth.pocket_box(grid)
+    params = _params(dk, lo, hi, pop_size=64, n_generations=2)
+
+    def cycle():
+        pocket = dk.dock_create_pocket(grid, maps, ff)
+        ligs = dk.dock_create_ligands(pocket, ligands)
+        out = _run_gpu_search(dk, pocket, ligs, params, 3, 12)
+        plan = dk.dock_search_plan_create(pocket, ligs, params, *[x.clone() for x in out[:4]])
+        dk.dock_search_plan_launch(plan)
+        net = dk.dock_mlp_create(0, 3)
+        torch.cuda.synchronize()
+        del plan, net, ligs, pocket, out
+        gc.collect()
+        torch.cuda.synchronize()
+
+    cycle()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(20):
+        cycle()
+    torch.cuda.empty_cache()
+    free1 = torch.cuda.mem_get_info()[0]
+    print("free device memory drift over 20 cycles:", (free0 - free1) / 2**20, "MiB", flush=True)
+    assert free0 - free1 < 32 * 2**20

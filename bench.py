@@ -158,11 +158,18 @@ def cpu_baseline(S, target_seconds: float, max_poses: int):
     while True:
         g = S["g"][:n]
         t0 = time.perf_counter()
-        oracle.score_poses(S["grid"], maps, S["ff"], [S["lig"]], g, n_threads=threads)
+        e_ora = oracle.score_poses(S["grid"], maps, S["ff"], [S["lig"]], g, n_threads=threads)
         t = time.perf_counter() - t0
         if t >= target_seconds or n >= max_poses:
             break
         n = min(max_poses, int(n * max(2.0, 1.2 * target_seconds / max(t, 1e-3))))
+    # the GPU's FP32 energies of the same poses (the last timed step) against the oracle's
+    e_gpu = S["e"][:n].cpu().numpy().astype(np.float64)
+    diff = np.abs(e_gpu - e_ora)
+    rel = diff / np.maximum(np.abs(e_ora), 1e-12)
+    tol = np.maximum(1e-4 * np.abs(e_ora), 1e-3)
+    parity = {"poses": int(n), "mean_rel_diff": float(np.mean(rel)), "median_rel_diff": float(np.median(rel)),
+              "max_abs_diff": float(diff.max()), "within_tolerance": float(np.mean(diff <= tol))}
     # one core, on a prefix sized to about a tenth of the threaded run's time
     n1 = max(200, int(n / threads / 10))
     t0 = time.perf_counter()
@@ -171,6 +178,7 @@ def cpu_baseline(S, target_seconds: float, max_poses: int):
     return {"value": n / t, "unit": "poses/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of the 1e7 genotypes, scored in {t:.1f} s (FP64, {threads} threads)",
             "one_core": {"value": round(n1 / t1, 1), "unit": "poses/s", "sample": f"first {n1} genotypes, {t1:.1f} s"},
+            "parity": parity,
             "host": host_info(),
             "search": cpu_search_baseline(threads)}
 

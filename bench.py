@@ -47,7 +47,7 @@ PAPER_CONTEXT = {
     "hardware": ["GH200 Grace 72 cores 2.5 GHz", "Xeon Platinum 8470 2x52 cores 2.5 GHz",
                  "EPYC 9684X 96 cores 2.7 GHz", "A64FX FX700 48 cores 2.0 GHz", "Graviton 4 96 cores (AWS)"],
     "precision": "FP32; fast math changes scores by under 0.0002% on average (Sec. VII)",
-    "run_to_run": "about 1% sigma/mean over 10 runs after 3 dropped (Sec. VII)",
+    "run_to_run": "about 1% sigma/mean over 10 runs after 3 dropped (Sec. VIII)",
     "workload": "100 individuals x 1000 generations per ligand; ~2500 MEDIATE ligands; 1a30 replicated (Sec. VII)",
     "bound": "compute-bound on one core per its roofline analysis (Sec. VIII, Tables IV-V)",
 }

@@ -466,3 +466,43 @@ def test_trained_network_gains(dk):
     t_plain, _ = pr.time_to_level(plain, level)
     t_learned, _ = pr.time_to_level(learned, level)
     assert t_learned is not None and t_learned < t_plain, (t_learned, t_plain)
+
+
+def test_non_finite_proposals_fall_back_to_plain_de(dk):
+    """Plain DE stays the fallback: a network whose outputs overflow (large
+    hidden activations times output weights near the float maximum) proposes
+    non-finite genes, every proposal scores NaN and none is taken, so the
+    search with proposal rounds is the plain search to the bit (the DE draws do
+    not depend on the proposals)."""
+    ff, rec, grid, maps = system(0)
+    ligands = [synth.make_ligand(2, 900 + i, n, t, 8) for i, (n, t) in enumerate([(14, 3), (24, 6), (40, 9)])]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    L = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + 9
+    net = dk.dock_mlp_create(0, 4)
+    p = dk.dock_mlp_get_params(net)
+    n_in, n_h, n_out = dk.DOCK_MLP_IN, 256, dk.DOCK_MLP_OUT
+    off_b2 = n_in * n_h + n_h + n_h * n_h
+    off_w3 = off_b2 + n_h
+    p[off_b2:off_w3] = 100.0                      # second-layer activations about 100
+    p[off_w3:off_w3 + n_h * n_out] = 3e38         # output weights near the float maximum
+    p[off_w3 + n_h * n_out:] = 0.0
+    assert off_w3 + n_h * n_out + n_out == p.size
+    dk.dock_mlp_set_params(net, p)
+    base = dk.SearchParams(pop_size=48, n_generations=20, seed=6, box_lo=tuple(lo), box_hi=tuple(hi))
+    from dataclasses import replace
+    from paper_2509_12232_amd import proposal as pr
+    outs = []
+    for prm in (base, replace(base, proposal=net, proposal_step=1.0, proposal_every=1, proposal_until=20)):
+        B = pr._buffers(3, 48, stride)
+        dk.dock_search(pocket, L, prm, B["pop"], B["pe"], B["bg"], B["be"])
+        torch.cuda.synchronize()
+        outs.append([B[k].cpu().numpy() for k in ("pop", "pe", "bg", "be")])
+    # the proposals really are non-finite
+    prop = torch.empty_like(torch.from_numpy(outs[0][0])).cuda()
+    dk.dock_propose(L, net, base, 20, 1.0, torch.from_numpy(outs[0][0]).cuda(), prop)
+    torch.cuda.synchronize()
+    assert not torch.isfinite(prop[:, :, 3:7]).any()     # every proposed orientation
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))

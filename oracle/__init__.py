@@ -25,13 +25,16 @@ __all__ = ["build", "load", "score_poses", "build_maps", "pose", "ligand_info", 
            "search", "SearchParams", "default_threads"]
 
 
-def build() -> str:
-    """Compile ``liboracle.so`` with gcc (IEEE binary64, no contraction, no fast-math)."""
+def build(out: str | None = None, extra_flags=()) -> str:
+    """Compile ``liboracle.so`` with gcc (IEEE binary64, no contraction, no
+    fast-math); ``out`` and ``extra_flags`` serve other builds of the same source
+    (the tests' instrumented one)."""
+    path = out or _LIB
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-pthread", _SRC, "-o", _LIB + ".tmp", "-lm"]
+           "-shared", "-pthread", *extra_flags, _SRC, "-o", path + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(path + ".tmp", path)
+    return path
 
 
 _lib = None
@@ -41,9 +44,12 @@ def load():
     """Load the built library (building it only if no build exists)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = C.CDLL(_LIB)
+        path = os.environ.get("ORACLE_LIB")   # another build of the same source (the sanitized one)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        lib = C.CDLL(path)
         lib.oracle_last_error.restype = C.c_char_p
         lib.oracle_pair_energy.restype = C.c_double
         lib.oracle_pair_energy.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double]

@@ -391,7 +391,10 @@ def learned_vs_plain():
     prop = pr.ProposalConfig()
     learned_pts, lbuf = pr.anytime(B["pocket"], L_ev, P, stride, net, prop, reference_best=ref_best)
     from dataclasses import replace
-    plain2_pts, _ = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, reference_best=ref_best)
+    plain2_pts, buf2 = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, reference_best=ref_best)
+    # the same comparison with seed 2 on both sides (its own plain level)
+    level2 = float(np.median(buf2["be"].cpu().numpy())) + 0.1
+    learned2_pts, _ = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, net, prop, reference_best=ref_best)
     # ligand level, with every ligand stopping at its target
     stops = {"plain_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target),
              "plain_seed2": pr.time_to_target(B["pocket"], L_ev, replace(P, seed=2), stride, target),
@@ -407,6 +410,8 @@ def learned_vs_plain():
     tp_ms, tp_gen = pr.time_to_level(plain_pts, level)
     tl_ms, tl_gen = pr.time_to_level(learned_pts, level)
     t2_ms, t2_gen = pr.time_to_level(plain2_pts, level)
+    s2_plain, _ = pr.time_to_level(plain2_pts, level2)
+    s2_learned, s2_gen = pr.time_to_level(learned2_pts, level2)
     rnd = (lambda v: None if v is None else round(v, 1))
     return {
         "workload": f"{L_ev.n} ligands (atoms lognormal median 32, 8-96; 0-20 torsions), 14 fp32 maps at 80^3, "
@@ -416,6 +421,9 @@ def learned_vs_plain():
         "batch_generations_to_level": {"plain_seed1": rnd(tp_gen), "plain_seed2": rnd(t2_gen),
                                        "learned_seed1": rnd(tl_gen)},
         "speedup_vs_plain_seed1": round(tp_ms / tl_ms, 3) if tp_ms and tl_ms else None,
+        "seed2": {"level": round(level2, 4), "plain_ms": rnd(s2_plain), "learned_ms": rnd(s2_learned),
+                  "learned_generations": rnd(s2_gen),
+                  "speedup": round(s2_plain / s2_learned, 3) if s2_plain and s2_learned else None},
         "median_best_at_end": {"plain_seed1": round(plain_pts[-1][2], 4), "plain_seed2": round(plain2_pts[-1][2], 4),
                                "learned_seed1": round(learned_pts[-1][2], 4)},
         "gpu_ms_at_end": {"plain_seed1": round(plain_pts[-1][1], 1), "plain_seed2": round(plain2_pts[-1][1], 1),

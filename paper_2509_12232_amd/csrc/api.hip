@@ -618,8 +618,8 @@ extern "C" dock_status dock_destroy_ligands(dock_ligands *L) {
 // Lanes per pose of the scoring kernel: 0 = automatic (score_lanes_auto).
 static std::atomic<int32_t> g_score_lanes{0};
 
-// Automatic shape, from measurements on MI355X (config-1 maps, 4e6 poses, one
-// ligand of each size): up to 32 atoms the three shapes are within 1%; at 40
+// Automatic shape, from measurements on MI355X (fourteen 100^3 maps, 4e6 random
+// poses of one ligand of each size): up to 32 atoms the three shapes are within 1%; at 40
 // atoms two lanes are fastest (+16% over one: the one-lane wavefront's LDS, 3
 // floats per atom per pose, leaves five wavefronts per CU); above that four
 // lanes (+37% at 48 atoms, +106% at 96, where the pair terms dominate and are

@@ -98,14 +98,22 @@ typedef struct {
  *                       an atom reads the one of its charge's sign (q E + |q| D
  *                       is q (E + D) for q >= 0 and q (E - D) for q < 0): two
  *                       cache lines per lookup (about 4.6x);
- *   DOCK_LAYOUT_AUTO    the quad-line layout if its copy fits 512 MiB, else z-pair.
- * Results do not depend on the layout beyond float rounding of the same terms. */
+ *   DOCK_LAYOUT_PAIRLINE one copy per (atom type, charge sign), each node's
+ *                       type quad followed by its E + D or E - D quad, four
+ *                       x-consecutive nodes to a 128-byte line (consecutive
+ *                       lines share one node): one cache line per lookup
+ *                       (about 14x for 12 types);
+ *   DOCK_LAYOUT_AUTO    the pair-line layout if its copy fits 8 GiB, else the
+ *                       quad-line layout if its copy fits 512 MiB, else z-pair.
+ * Results do not depend on the layout beyond float rounding of the same terms;
+ * the quad-line and pair-line layouts give the same bits. */
 enum {
   DOCK_LAYOUT_AUTO = -1,
   DOCK_LAYOUT_LINEAR = 0,
   DOCK_LAYOUT_ZPAIR = 1,
   DOCK_LAYOUT_YZQUAD = 2,
-  DOCK_LAYOUT_QUADLINE = 3
+  DOCK_LAYOUT_QUADLINE = 3,
+  DOCK_LAYOUT_PAIRLINE = 4
 };
 
 /* Create a pocket from precomputed maps (Sec. V: maps precomputed around the
@@ -113,7 +121,8 @@ enum {
  * pointer in the layout above.  layout: one of DOCK_LAYOUT_*.  device: HIP
  * device ordinal.  *out receives the handle.  Synchronous.  Errors:
  * DOCK_E_INVALID (null pointers, n_types mismatch, dims < 2, spacing <= 0, map
- * larger than 2^31 floats, unknown layout), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+ * larger than 2^31 floats, unknown layout, a quad-line or pair-line map of more
+ * than 2^31 elements), DOCK_E_NOMEM, DOCK_E_DEVICE. */
 dock_status dock_create_pocket(const dock_grid *grid, const float *maps, int32_t maps_on_device,
                                const dock_forcefield *ff, int32_t layout, int32_t device, dock_pocket **out);
 
@@ -186,13 +195,15 @@ dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs
  * for every shape): lanes_per_pose = 1, 2 or 4 lanes build and score one pose
  * together, a wavefront then holds 64 / lanes_per_pose poses and needs
  * 1 / lanes_per_pose of the LDS, so more wavefronts stay resident for large
- * ligands; 0 restores the automatic choice by the set's largest ligand.
- * Process-wide; takes effect at the next call.  Errors: DOCK_E_INVALID for any
+ * ligands; 0 restores the automatic choice by the set's largest ligand and the
+ * pocket's map layout.  Process-wide; takes effect at the next call.  Errors: DOCK_E_INVALID for any
  * other value. */
 dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose);
 
-/* The lanes per pose dock_score_poses uses for ligand set ligs (the setting
- * above, or the automatic choice).  Errors: DOCK_E_INVALID (null argument). */
+/* The lanes per pose dock_score_poses uses for ligand set ligs with the pocket
+ * it was created for (the setting above, or the automatic choice, which depends
+ * on the set's largest ligand and the pocket's map layout).  Errors:
+ * DOCK_E_INVALID (null argument). */
 dock_status dock_score_lanes_per_pose(const dock_ligands *ligs, int32_t *lanes_per_pose);
 
 /* Differential evolution (DE/rand/1/bin, greedy selection) as the evolutionary

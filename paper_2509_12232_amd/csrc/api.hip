@@ -72,31 +72,59 @@ hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s) {
 extern "C" int32_t dock_version(void) { return 1; }
 
 // ------------------------------------------------------------------------------ handles
-// Packed layout for the scoring kernel: the quad-line layout (two cache lines
-// per lookup, about 4.6x the ABI maps) while its copy stays within kQuadBudget
-// bytes, so that the part the ligands reach stays resident in the 256 MB
-// Infinity Cache; else the z-pair layout (2x).
+// Packed layout for the scoring kernel: the pair-line layout (one cache line
+// per lookup, about 14x the ABI maps) while its copy stays within kPairBudget
+// bytes; else the quad-line layout (two lines per lookup, about 4.6x) within
+// kQuadBudget; else the z-pair layout (2x).  Random lookups are bound by the
+// lines in flight per CU, so halving the lines per lookup outweighs the pair-line
+// copy outgrowing the 256 MB Infinity Cache (measured on MI355X with fourteen
+// 100^3 maps: 58 against 37 G lookups/s).
+static constexpr double kPairBudget = 8.0 * 1024 * 1024 * 1024;
 static constexpr double kQuadBudget = 512.0 * 1024 * 1024;
 
 static int64_t line_blocks(const MapGeom &g) { return (g.nx - 2) / kLineCells + 1; }
 static int64_t line_stride(const MapGeom &g) {
   return (int64_t)(g.nz - 1) * (g.ny - 1) * line_blocks(g) * kLineQuads;
 }
+static int64_t pair_blocks(const MapGeom &g) { return (g.nx - 2) / kPairCells + 1; }
+static int64_t pair_stride(const MapGeom &g) {
+  return (int64_t)(g.nz - 1) * (g.ny - 1) * pair_blocks(g) * (2 * kPairNodes);
+}
+// Largest element index of one map (or copy) of each line layout, which the
+// gather computes in 32 bits.
+static double line_elements(const int32_t dims[3]) {
+  return (double)(dims[2] - 1) * (dims[1] - 1) * ((dims[0] - 2) / kLineCells + 1) * kLineQuads;
+}
+static double pair_elements(const int32_t dims[3]) {
+  return (double)(dims[2] - 1) * (dims[1] - 1) * ((dims[0] - 2) / kPairCells + 1) * (2 * kPairNodes);
+}
 
 static int32_t choose_layout(const MapGeom &g, int32_t requested) {
   if (requested != DOCK_LAYOUT_AUTO) return requested;
+  const int32_t dims[3] = {g.nx, g.ny, g.nz};
+  const double pair_bytes = (double)pair_stride(g) * 16.0 * (2 * g.n_types);
+  if (pair_bytes <= kPairBudget && pair_elements(dims) <= 2147483647.0) return kPairLine;
   const double bytes = (double)line_stride(g) * 16.0 * (g.n_types + 2);
   return bytes <= kQuadBudget ? kQuadLine : kZPair;
 }
 
 static bool valid_layout(int32_t layout) {
   return layout == DOCK_LAYOUT_AUTO || layout == DOCK_LAYOUT_LINEAR || layout == DOCK_LAYOUT_ZPAIR ||
-         layout == DOCK_LAYOUT_YZQUAD || layout == DOCK_LAYOUT_QUADLINE;
+         layout == DOCK_LAYOUT_YZQUAD || layout == DOCK_LAYOUT_QUADLINE || layout == DOCK_LAYOUT_PAIRLINE;
 }
 
 // Builds the packed copy of p->maps (already on the device).
 static hipError_t pack_maps(dock_pocket *p, int32_t requested) {
   p->layout = choose_layout(p->geom, requested);
+  if (p->layout == kPairLine) {
+    p->nxb = (int32_t)pair_blocks(p->geom);
+    p->t_stride = pair_stride(p->geom);
+    hipError_t e = hipMalloc(&p->tpack, (size_t)p->t_stride * 16 * (2 * p->geom.n_types));
+    if (e == hipSuccess)
+      e = launch_relayout_pairs(p->geom, p->nxb, p->t_stride, p->maps, (float4 *)p->tpack, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    return e;
+  }
   if (p->layout == kQuadLine) {
     p->nxb = (int32_t)line_blocks(p->geom);
     p->t_stride = line_stride(p->geom);
@@ -158,10 +186,11 @@ static dock_status check_grid(const dock_grid *g, int n_types, int32_t layout) {
     if (!isfinite(g->origin[d])) return set_err(DOCK_E_INVALID, "non-finite origin");
   const double total = (double)g->dims[0] * g->dims[1] * g->dims[2] * (n_types + 2);
   if (total > 2147483647.0) return set_err(DOCK_E_INVALID, "maps larger than 2^31 values");
-  // the quad-line gather indexes one map with 32-bit element indices
-  const double lines = (double)(g->dims[2] - 1) * (g->dims[1] - 1) * ((g->dims[0] - 2) / kLineCells + 1) * kLineQuads;
-  if (layout == DOCK_LAYOUT_QUADLINE && lines > 2147483647.0)
+  // the line layouts' gathers index one map (or copy) with 32-bit element indices
+  if (layout == DOCK_LAYOUT_QUADLINE && line_elements(g->dims) > 2147483647.0)
     return set_err(DOCK_E_INVALID, "grid too large for the quad-line layout");
+  if (layout == DOCK_LAYOUT_PAIRLINE && pair_elements(g->dims) > 2147483647.0)
+    return set_err(DOCK_E_INVALID, "grid too large for the pair-line layout");
   return DOCK_OK;
 }
 
@@ -561,6 +590,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
   HIP_TRY(ds.err, "hipSetDevice");
   dock_ligands *L = new dock_ligands();
   L->device = pocket->device;
+  L->layout = pocket->layout;
   L->n_ligs = n_ligands;
   L->max_atoms = max_atoms;
   L->max_tors = max_tors;
@@ -619,20 +649,23 @@ extern "C" dock_status dock_destroy_ligands(dock_ligands *L) {
 static std::atomic<int32_t> g_score_lanes{0};
 
 // Automatic shape, from measurements on MI355X (fourteen 100^3 maps, 4e6 random
-// poses of one ligand of each size): up to 32 atoms the three shapes are within 1%; at 40
-// atoms two lanes are fastest (+16% over one: the one-lane wavefront's LDS, 3
-// floats per atom per pose, leaves five wavefronts per CU); above that four
-// lanes (+37% at 48 atoms, +106% at 96, where the pair terms dominate and are
-// split four ways).
-static int32_t score_lanes_auto(int32_t max_atoms) {
+// poses of one ligand of each size).  The one-lane wavefront's LDS (3 floats per
+// atom per pose) leaves five wavefronts per CU at 40 atoms; more lanes split the
+// pair terms.  With the pair-line maps two lanes are fastest from 12 to 64 atoms
+// (+12% over one at 32 atoms, +7% over four at 48), four above (+21% at 96).
+// With the other layouts, whose lookups take longer: up to 32 atoms the three
+// shapes are within 1%, at 40 two lanes are fastest (+16% over one), above that
+// four (+7% over two at 48 atoms, +44% at 96).
+static int32_t score_lanes_auto(int32_t max_atoms, int32_t layout) {
+  if (layout == kPairLine) return max_atoms <= 64 ? 2 : 4;
   if (max_atoms <= 32) return 1;
   if (max_atoms <= 40) return 2;
   return 4;
 }
 
-static int32_t score_lanes(const dock_ligands *L) {
+static int32_t score_lanes(const dock_ligands *L, int32_t layout) {
   const int32_t lp = g_score_lanes.load();
-  return lp ? lp : score_lanes_auto(L->max_atoms);
+  return lp ? lp : score_lanes_auto(L->max_atoms, layout);
 }
 
 extern "C" dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose) {
@@ -644,7 +677,7 @@ extern "C" dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose) {
 
 extern "C" dock_status dock_score_lanes_per_pose(const dock_ligands *L, int32_t *lanes_per_pose) {
   if (!L || !lanes_per_pose) return set_err(DOCK_E_INVALID, "null argument");
-  *lanes_per_pose = score_lanes(L);
+  *lanes_per_pose = score_lanes(L, L->layout);
   return DOCK_OK;
 }
 
@@ -656,7 +689,7 @@ static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
   a.maps = p->view();
   a.layout = p->layout;
   a.lds_atoms = L->max_atoms;
-  a.lanes_per_pose = score_lanes(L);
+  a.lanes_per_pose = score_lanes(L, p->layout);
   return a;
 }
 
@@ -1197,7 +1230,7 @@ extern "C" dock_status dock_search_tune_load(const char *path) {
     char extra[2];
     const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %1s", arch, &k.n_cu, &k.layout, &k.nx, &k.ny,
                            &k.nz, &k.n_types, &k.upper, &k.lds_atoms, &k.pop, &sh.lanes_per_pose, &sh.waves, extra);
-    const bool valid = got == 12 && k.n_cu > 0 && k.layout >= kLinear && k.layout <= kQuadLine && k.nx >= 2 &&
+    const bool valid = got == 12 && k.n_cu > 0 && k.layout >= kLinear && k.layout <= kPairLine && k.nx >= 2 &&
                        k.ny >= 2 && k.nz >= 2 && k.n_types >= 1 && k.n_types <= kMaxTypes && k.upper >= 1 &&
                        k.upper <= kMaxAtoms && k.lds_atoms >= 1 && k.lds_atoms <= k.upper && k.pop >= 4 &&
                        (sh.lanes_per_pose == 1 || sh.lanes_per_pose == 2 || sh.lanes_per_pose == 4) &&

@@ -67,7 +67,7 @@ struct dock_pocket {
   int32_t layout = dock::kLinear;    // layout the scoring kernel reads
   int32_t n_cu = 1;            // compute units of the device (persistent launch size)
   std::string arch;            // device architecture name (keys the autotuner's cache)
-  void *tpack = nullptr;       // packed type maps (kQuadLine: all maps)
+  void *tpack = nullptr;       // packed type maps (kQuadLine, kPairLine: all maps)
   float4 *edpack = nullptr;    // packed electrostatic/desolvation records
   int64_t t_stride = 0;
   int32_t nxb = 0;
@@ -79,6 +79,7 @@ struct dock_pocket {
     if (layout == dock::kZPair) m.tz = (const float2 *)tpack, m.edz = edpack;
     if (layout == dock::kYZQuad) m.tq = (const float4 *)tpack, m.edq = edpack;
     if (layout == dock::kQuadLine) m.lq = (const float4 *)tpack;
+    if (layout == dock::kPairLine) m.pq = (const float4 *)tpack;
     return m;
   }
 };
@@ -97,6 +98,7 @@ struct dock_ligands {
   int device = 0;
   int n_ligs = 0;
   int max_atoms = 0, max_tors = 0;
+  int32_t layout = dock::kLinear;   // map layout of the pocket the set was created for
   std::vector<dock::LigHeader> hdr_host;
   std::vector<int32_t> pair_count;
   dock::LigHeader *hdr = nullptr;

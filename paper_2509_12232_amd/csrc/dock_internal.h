@@ -66,11 +66,19 @@ struct MapGeom {
 //            signed maps S+ = E + D and S- = E - D: since q E + |q| D equals
 //            q S+ for q >= 0 and q S- for q < 0, one lookup reads a type quad pair
 //            and one signed quad pair, exactly two cache lines.
-enum MapLayout : int32_t { kLinear = 0, kZPair = 1, kYZQuad = 2, kQuadLine = 3 };
+//   kPairLine: one copy per (atom type, charge sign): node x of a row is its
+//            type quad followed by its signed quad (32 B), four x-consecutive
+//            nodes to a 128-byte line, x = 3k .. 3k+3 in line k, so a lookup
+//            (both nodes of its cell, both quads of each) is 64 contiguous
+//            bytes of one cache line.  2 n_types copies, about 14x the ABI maps.
+enum MapLayout : int32_t { kLinear = 0, kZPair = 1, kYZQuad = 2, kQuadLine = 3, kPairLine = 4 };
 
 // Quads per line of kQuadLine and the cells (x steps) a line covers.
 constexpr int kLineQuads = 8;
 constexpr int kLineCells = kLineQuads - 1;
+// Nodes per line of kPairLine (two quads each) and the cells a line covers.
+constexpr int kPairNodes = 4;
+constexpr int kPairCells = kPairNodes - 1;
 
 struct MapData {
   const float *lin;      // [n_types+2][nz][ny][nx]
@@ -80,8 +88,11 @@ struct MapData {
   const float4 *edq;     // kYZQuad E/D:   [nz-1][ny-1][nx][2]
   const float4 *lq;      // kQuadLine:     [n_types + 2][nz-1][ny-1][nxb][kLineQuads], maps n_types and
                          //                n_types+1 are S+ and S-
-  int64_t t_stride;      // elements (quads) per map in the packed layout
-  int32_t nxb;           // kQuadLine: lines per (y, z) row, (nx - 2) / kLineCells + 1
+  const float4 *pq;      // kPairLine:     [2 n_types][nz-1][ny-1][nxb][kPairNodes][2]: copy 2t + s
+                         //                holds type t's quads and S+ (s = 0) or S- (s = 1)
+  int64_t t_stride;      // elements (quads) per map (kPairLine: per copy) in the packed layout
+  int32_t nxb;           // lines per (y, z) row: kQuadLine (nx - 2) / kLineCells + 1,
+                         // kPairLine (nx - 2) / kPairCells + 1
 };
 
 struct FFConst {

@@ -27,5 +27,8 @@ hipError_t launch_relayout(const MapGeom &g, int32_t layout, const float *lin, v
 // The kQuadLine copy: (n_types + 2) maps of t_stride quads, nxb lines per row.
 hipError_t launch_relayout_lines(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
                                  hipStream_t s);
+// The kPairLine copy: 2 n_types copies of t_stride quads, nxb lines per row.
+hipError_t launch_relayout_pairs(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
+                                 hipStream_t s);
 
 }  // namespace dock

@@ -136,6 +136,56 @@ __global__ void relayout_lines_kernel(MapGeom g, int32_t nxb, int64_t t_stride, 
   out[(g.n_types + 1) * t_stride + e] = make_float4(E.x - D.x, E.y - D.y, E.z - D.z, E.w - D.w);
 }
 
+// kPairLine: one thread per node slot of a line (slot j of line k is node
+// x = kPairCells k + j); it writes that slot's type quad and signed quad in
+// every (type, sign) copy.  Slots past the row's last node are zero and never
+// read.  S+ and S- are rounded exactly as in kQuadLine, so the two layouts give
+// the same energies.
+__global__ void relayout_pairs_kernel(MapGeom g, int32_t nxb, int64_t t_stride, const float *__restrict__ lin,
+                                      float4 *__restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // node slot index
+  if (n >= t_stride / 2) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int slot = (int)(n % kPairNodes);
+  const int64_t line = n / kPairNodes;
+  const int k = (int)(line % nxb);
+  const int y = (int)((line / nxb) % (ny - 1));
+  const int z = (int)(line / ((int64_t)nxb * (ny - 1)));
+  const int x = k * kPairCells + slot;
+  const int64_t e = 2 * n;   // quad index of the slot's type quad within a copy
+  const int64_t plane = (int64_t)nx * ny * nz;
+  if (x >= nx) {
+    for (int c = 0; c < 2 * g.n_types; ++c) {
+      out[c * t_stride + e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[c * t_stride + e + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
+  auto quad = [&](int m) {
+    const float *M = lin + m * plane;
+    const int64_t o = ((int64_t)z * ny + y) * nx + x;
+    return make_float4(M[o], M[o + nx], M[o + (int64_t)nx * ny], M[o + (int64_t)nx * ny + nx]);
+  };
+  const float4 E = quad(g.n_types), D = quad(g.n_types + 1);
+  const float4 Sp = make_float4(E.x + D.x, E.y + D.y, E.z + D.z, E.w + D.w);
+  const float4 Sm = make_float4(E.x - D.x, E.y - D.y, E.z - D.z, E.w - D.w);
+  for (int t = 0; t < g.n_types; ++t) {
+    const float4 T = quad(t);
+    out[(2 * t) * t_stride + e] = T;
+    out[(2 * t) * t_stride + e + 1] = Sp;
+    out[(2 * t + 1) * t_stride + e] = T;
+    out[(2 * t + 1) * t_stride + e + 1] = Sm;
+  }
+}
+
+hipError_t launch_relayout_pairs(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
+                                 hipStream_t s) {
+  const int64_t nodes = t_stride / 2;
+  hipLaunchKernelGGL(relayout_pairs_kernel, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, s, g, nxb,
+                     t_stride, lin, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_relayout_lines(const MapGeom &g, int32_t nxb, int64_t t_stride, const float *lin, float4 *out,
                                  hipStream_t s) {
   hipLaunchKernelGGL(relayout_lines_kernel, dim3((unsigned)((t_stride + 255) / 256)), dim3(256), 0, s, g, nxb,

@@ -92,6 +92,8 @@ hipError_t launch_gather_probe(const MapGeom &G, const MapData &M, int32_t layou
     case kYZQuad: return launch_gather_probe_t<kYZQuad>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
     case kQuadLine:
       return launch_gather_probe_t<kQuadLine>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
+    case kPairLine:
+      return launch_gather_probe_t<kPairLine>(G, M, L, lig, box, n_lanes, per_lane, in_flight, seed, out, s);
   }
   return hipErrorInvalidValue;
 }

@@ -69,6 +69,7 @@ hipError_t launch_score(const ScoreLaunch &a, hipStream_t s) {
     case kZPair: return launch_score_t<kZPair>(a, s);
     case kYZQuad: return launch_score_t<kYZQuad>(a, s);
     case kQuadLine: return launch_score_t<kQuadLine>(a, s);
+    case kPairLine: return launch_score_t<kPairLine>(a, s);
   }
   return hipErrorInvalidValue;
 }

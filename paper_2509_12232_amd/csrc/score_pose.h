@@ -84,6 +84,10 @@ struct Corners<kQuadLine> {
   }
 };
 
+// kPairLine loads the same four quads, from one line.
+template <>
+struct Corners<kPairLine> : Corners<kQuadLine> {};
+
 // Trilinear interpolation of (T_type + q E + |q| D) from loaded corners; 0 outside
 // the closed grid box (Algorithm 2's "nearby" test).
 template <int LAYOUT>
@@ -143,7 +147,7 @@ __device__ __forceinline__ Corners<LAYOUT> gather_corners(const MapGeom &G, cons
     const float4 *T = M.tq + (size_t)type * M.t_stride;
     C.t0 = T[e]; C.t1 = T[e + 1];
     C.e0 = M.edq[2 * e]; C.d0 = M.edq[2 * e + 1]; C.e1 = M.edq[2 * e + 2]; C.d1 = M.edq[2 * e + 3];
-  } else {
+  } else if constexpr (LAYOUT == kQuadLine) {
     // line k = cx / 7 of row (cy, cz), slot cx - 7k in [0, 6]: both quads in one line
     const int k = cx / kLineCells;
     const int e = ((cz * (G.ny - 1) + cy) * M.nxb + k) * kLineQuads + (cx - k * kLineCells);
@@ -151,6 +155,14 @@ __device__ __forceinline__ Corners<LAYOUT> gather_corners(const MapGeom &G, cons
     const float4 *Sg = M.lq + (size_t)(G.n_types + (q < 0.f ? 1 : 0)) * M.t_stride;
     C.t0 = T[e]; C.t1 = T[e + 1];
     C.s0 = Sg[e]; C.s1 = Sg[e + 1];
+  } else {
+    // line k = cx / 3 of row (cy, cz) in the atom's (type, sign) copy, node slot
+    // cx - 3k in [0, 2]: (T, S) of node x, then of node x + 1, 64 contiguous bytes
+    const int k = cx / kPairCells;
+    const int e = ((cz * (G.ny - 1) + cy) * M.nxb + k) * (2 * kPairNodes) + 2 * (cx - k * kPairCells);
+    const float4 *B = M.pq + (size_t)(2 * type + (q < 0.f ? 1 : 0)) * M.t_stride;
+    C.t0 = B[e]; C.s0 = B[e + 1];
+    C.t1 = B[e + 2]; C.s1 = B[e + 3];
   }
   return C;
 }

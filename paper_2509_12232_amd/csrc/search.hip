@@ -428,6 +428,7 @@ hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, Se
     case kZPair: return launch_search_lp<kZPair>(S, n_cu, shape, s, step);
     case kYZQuad: return launch_search_lp<kYZQuad>(S, n_cu, shape, s, step);
     case kQuadLine: return launch_search_lp<kQuadLine>(S, n_cu, shape, s, step);
+    case kPairLine: return launch_search_lp<kPairLine>(S, n_cu, shape, s, step);
   }
   return hipErrorInvalidValue;
 }

@@ -24,7 +24,8 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 DOCK_OK, DOCK_E_INVALID, DOCK_E_NOMEM, DOCK_E_DEVICE, DOCK_E_UNSUPPORTED = range(5)
-DOCK_LAYOUT_AUTO, DOCK_LAYOUT_LINEAR, DOCK_LAYOUT_ZPAIR, DOCK_LAYOUT_YZQUAD, DOCK_LAYOUT_QUADLINE = -1, 0, 1, 2, 3
+(DOCK_LAYOUT_AUTO, DOCK_LAYOUT_LINEAR, DOCK_LAYOUT_ZPAIR, DOCK_LAYOUT_YZQUAD, DOCK_LAYOUT_QUADLINE,
+ DOCK_LAYOUT_PAIRLINE) = -1, 0, 1, 2, 3, 4
 _STATUS = {1: "DOCK_E_INVALID", 2: "DOCK_E_NOMEM", 3: "DOCK_E_DEVICE", 4: "DOCK_E_UNSUPPORTED"}
 
 

@@ -36,7 +36,7 @@ def test_config1_full_size_sampled_parity(ora):
     print("case: config1 full size, oracle maps 100^3", flush=True)
     maps = ora.build_maps(ff, rec, grid)
     pocket = dk.dock_create_pocket(grid, maps, ff)
-    assert pocket.layout == dk.DOCK_LAYOUT_QUADLINE
+    assert pocket.layout == dk.DOCK_LAYOUT_PAIRLINE
     ligs = dk.dock_create_ligands(pocket, [lig])
     lo, hi = synth.pocket_box(grid)
     g = synth.sample_genotypes(1, N_POSES, lig.n_torsions, 7 + lig.n_torsions, lo, hi)

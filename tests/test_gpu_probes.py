@@ -16,7 +16,7 @@ def test_probes_run_and_validate():
     ff, rec, grid, maps = system(0)
     lig = synth.make_ligand(1, 0, 24, 6, 8)
     lo, hi = synth.pocket_box(grid)
-    for layout in (0, 1, 2, 3):
+    for layout in (0, 1, 2, 3, 4):
         pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
         ligs = dk.dock_create_ligands(pocket, [lig])
         for in_flight in (2, 4, 8):

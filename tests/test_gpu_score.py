@@ -28,7 +28,7 @@ def _gpu_energies(dk, pocket, ligs, g, pose_ligand=None):
     return e.cpu().numpy()
 
 
-@pytest.mark.parametrize("layout", [0, 1, 2, 3])
+@pytest.mark.parametrize("layout", [0, 1, 2, 3, 4])
 def test_config0_single_ligand_parity(dk, ora, layout):
     """24-atom, 6-torsion ligand on 40^3 maps: 4133 random poses (64 full tiles +
     a ragged tail), for each device map layout."""
@@ -47,11 +47,38 @@ def test_config0_single_ligand_parity(dk, ora, layout):
     assert_energies_match(e_gpu, e_ref, keep)
 
 
+def test_pair_line_gives_the_quad_line_bits(dk):
+    """The pair-line and quad-line layouts hold the same rounded values (type
+    quads, E + D and E - D quads) and the kernel interpolates them in the same
+    order, so energies are the same bits in every lanes-per-pose shape, for atoms
+    of both charge signs and for poses reaching past the grid box."""
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    assert (lig.charge > 0).any() and (lig.charge < 0).any()
+    lo = np.asarray(grid.origin) - 1.0
+    hi = np.asarray(grid.upper()) + 1.0
+    g = synth.sample_genotypes(12, 2077, 6, 13, lo, hi)
+    got = {}
+    try:
+        for layout in (3, 4):
+            pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+            ligs = dk.dock_create_ligands(pocket, [lig])
+            for lp in (1, 2, 4):
+                print("case: quad-line vs pair-line bits, layout", layout, "lanes", lp, flush=True)
+                dk.dock_score_set_lanes_per_pose(lp)
+                got[layout, lp] = _gpu_energies(dk, pocket, ligs, g)
+    finally:
+        dk.dock_score_set_lanes_per_pose(0)
+    for lp in (1, 2, 4):
+        assert np.array_equal(got[3, lp].view(np.uint32), got[4, lp].view(np.uint32)), lp
+    assert np.isfinite(got[4, 1]).all()
+
+
 @pytest.mark.parametrize("dims", [(2, 2, 2), (9, 3, 5), (16, 7, 4), (23, 11, 6)])
 def test_odd_grid_dims_every_layout(dk, ora, dims):
-    """Non-cubic grids whose x extent leaves the quad-line layout a partly
-    filled last line per row (and the 2-node minimum), with poses spread over
-    and past the grid box, for every device layout."""
+    """Non-cubic grids whose x extent leaves the quad-line and pair-line layouts
+    a partly filled last line per row (and the 2-node minimum), with poses spread
+    over and past the grid box, for every device layout."""
     import oracle
     nt = 8
     ff = synth.forcefield(nt)
@@ -64,7 +91,7 @@ def test_odd_grid_dims_every_layout(dk, ora, dims):
     g = synth.sample_genotypes(21, 700, 3, 10, lo, hi)
     e_ref = ora.score_poses(grid, maps, ff, [lig], g)
     keep = near_face_mask(ora, grid, [lig], g)
-    for layout in (0, 1, 2, 3):
+    for layout in (0, 1, 2, 3, 4):
         print("case: grid dims", dims, "layout", layout, flush=True)
         pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
         ligs = dk.dock_create_ligands(pocket, [lig])
@@ -227,7 +254,7 @@ def test_max_torsions_and_types(dk, ora):
     e_ref = ora.score_poses(grid, maps, ff, [lig], g)
     keep = near_face_mask(ora, grid, [lig], g)
     try:
-        for layout in (0, 1, 2, 3):
+        for layout in (0, 1, 2, 3, 4):
             pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
             ligs = dk.dock_create_ligands(pocket, [lig])
             for lp in (1, 2, 4):

@@ -212,6 +212,25 @@ def test_launch_shape_does_not_change_results(dk):
     assert np.all(reached[0][1] <= ref[3] + 0.1)
 
 
+def test_quad_line_and_pair_line_search_same_bits(dk):
+    """A whole search reads its maps through either line layout with the same
+    results bit for bit: populations, energies and bests."""
+    ff, rec, grid, maps = system(2, grid_n=48)
+    ligands = _ligs_cfg2(10)
+    lo, hi = synth.pocket_box(grid)
+    stride = 7 + max(l.n_torsions for l in ligands)
+    params = _params(dk, lo, hi, pop_size=50, n_generations=8)
+    runs = []
+    for layout in (dk.DOCK_LAYOUT_QUADLINE, dk.DOCK_LAYOUT_PAIRLINE):
+        print("case: search with layout", layout, flush=True)
+        pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+        assert pocket.layout == layout
+        ligs = dk.dock_create_ligands(pocket, ligands)
+        runs.append([x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]])
+    for x, y in zip(*runs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
 def test_tune_cache_file_applies_to_new_handles(dk, tmp_path):
     """Tuned shapes saved to a file name this device's kind, pocket and buckets;
     loaded back (edited), they are what a new handle for the same ligands uses,

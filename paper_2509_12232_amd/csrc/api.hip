@@ -651,13 +651,13 @@ static std::atomic<int32_t> g_score_lanes{0};
 // Automatic shape, from measurements on MI355X (fourteen 100^3 maps, 4e6 random
 // poses of one ligand of each size).  The one-lane wavefront's LDS (3 floats per
 // atom per pose) leaves five wavefronts per CU at 40 atoms; more lanes split the
-// pair terms.  With the pair-line maps two lanes are fastest from 12 to 64 atoms
-// (+12% over one at 32 atoms, +7% over four at 48), four above (+21% at 96).
-// With the other layouts, whose lookups take longer: up to 32 atoms the three
-// shapes are within 1%, at 40 two lanes are fastest (+16% over one), above that
-// four (+7% over two at 48 atoms, +44% at 96).
+// pair terms.  With the pair-line maps two lanes are fastest from 12 to 40 atoms
+// (+16% over one at 32 atoms, +7% over four at 40), four above (+8% over two at
+// 48 atoms, +17% at 64, +41% at 96).  With the other layouts, whose lookups take
+// longer: up to 32 atoms the three shapes are within 1%, at 40 two lanes are
+// fastest (+16% over one), above that four.
 static int32_t score_lanes_auto(int32_t max_atoms, int32_t layout) {
-  if (layout == kPairLine) return max_atoms <= 64 ? 2 : 4;
+  if (layout == kPairLine) return max_atoms <= 40 ? 2 : 4;
   if (max_atoms <= 32) return 1;
   if (max_atoms <= 40) return 2;
   return 4;

@@ -211,8 +211,15 @@ struct PairGroup {
 };
 
 // Record q R + u (u < R = 4 / LP) of four, for lane q of an LP-lane pose: the
-// lane picks its records out of the group's uniform ones.
-template <int LP>
+// lane picks its records out of the group's uniform ones.  SCALAR: the records
+// sit in scalar registers, and a vector instruction takes at most one scalar
+// operand, so a select first copies its candidates into vector registers.  With
+// four lanes that makes a three-way chain of selects costly, and the pick is
+// arithmetic instead: the sum of the candidates weighted by 0 or 1 (exact for
+// finite records up to the sign of a zero term, which no sum starting at +0
+// carries), and a masked or for the packed atom indices.  With two lanes, and
+// with records in vector registers, selects are cheaper.
+template <int LP, bool SCALAR>
 __device__ __forceinline__ PairRec lane_record(const PairRec r[4], int q, int u) {
   if constexpr (LP == 1) {
     return r[u];
@@ -225,7 +232,7 @@ __device__ __forceinline__ PairRec lane_record(const PairRec r[4], int q, int u)
     o.qq = q ? b.qq : a.qq;
     o.sv = q ? b.sv : a.sv;
     return o;
-  } else {
+  } else if constexpr (!SCALAR) {
     PairRec o = r[0];
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
@@ -236,12 +243,34 @@ __device__ __forceinline__ PairRec lane_record(const PairRec r[4], int q, int u)
       o.sv = q == k ? r[k].sv : o.sv;
     }
     return o;
+  } else {
+    float w[4];
+    int32_t m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[k] = q == k ? 1.f : 0.f;
+      m[k] = q == k ? -1 : 0;
+    }
+    PairRec o;
+    o.ij = (r[0].ij & m[0]) | (r[1].ij & m[1]) | (r[2].ij & m[2]) | (r[3].ij & m[3]);
+    o.A = r[0].A * w[0];
+    o.B = r[0].B * w[0];
+    o.qq = r[0].qq * w[0];
+    o.sv = r[0].sv * w[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      o.A = fmaf(r[k].A, w[k], o.A);
+      o.B = fmaf(r[k].B, w[k], o.B);
+      o.qq = fmaf(r[k].qq, w[k], o.qq);
+      o.sv = fmaf(r[k].sv, w[k], o.sv);
+    }
+    return o;
   }
 }
 
 // The R = 4 / LP pairs of a group that lane q of an LP-lane pose evaluates
 // (records q R .. q R + R - 1), with their atoms' coordinates.
-template <int STRIDE, int LP>
+template <int STRIDE, int LP, bool SCALAR>
 struct LaneGroupCoords {
   static constexpr int R = 4 / LP;
   float xi[R], yi[R], zi[R], xj[R], yj[R], zj[R];
@@ -249,7 +278,7 @@ struct LaneGroupCoords {
   __device__ __forceinline__ void load(const PairGroup &G, float *my, int q) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      r[u] = lane_record<LP>(G.r, q, u);
+      r[u] = lane_record<LP, SCALAR>(G.r, q, u);
       const int i = r[u].ij & 0xffff, j = r[u].ij >> 16;
       xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
       xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
@@ -280,8 +309,11 @@ __device__ __forceinline__ void wave_sync() {
 // pairs); lane h owns p_u for u in [h 4/LP, (h + 1) 4/LP).  So every LP gives
 // the same bits.  Non-finite genes give NaN.  AHEAD: how many pair slices ahead
 // of its use an atom's map loads are issued (more loads in flight, more
-// registers); it does not change the result.
-template <int STRIDE, int LAYOUT, int LP = 1, int AHEAD = 1>
+// registers); it does not change the result.  SCALAR: the kernel reads the
+// ligand tables with scalar loads (it stores nothing the compiler cannot tell
+// apart from them), which selects how lanes pick their pair records; it does
+// not change the result either.
+template <int STRIDE, int LAYOUT, int LP = 1, int AHEAD = 1, bool SCALAR = true>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
                             const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my) {
   static_assert(LP == 1 || LP == 2 || LP == 4, "one, two or four lanes per pose");
@@ -387,14 +419,14 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   PairGroup A, B;
   A.load(pairs);
   B.load(pairs + 4);
-  LaneGroupCoords<STRIDE, LP> X;
+  LaneGroupCoords<STRIDE, LP, SCALAR> X;
   X.load(A, my, h);
   for (int k = 0; k < slots; ++k) {
     const int ka = k + AHEAD;
     if (ka < slots) ring[AHEAD] = gather(ka);
     const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
     for (int gi = g0; gi < g1; ++gi) {
-      LaneGroupCoords<STRIDE, LP> Xn;
+      LaneGroupCoords<STRIDE, LP, SCALAR> Xn;
       Xn.load(B, my, h);
       PairGroup C;
       C.load(pairs + 4 * (gi + 2));
@@ -423,7 +455,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
 #pragma unroll
     for (int u = 0; u < 4; ++u) blk[u] = p + u < H.n_pairs_hb ? hb[p + u] : zero;
 #pragma unroll
-    for (int u = 0; u < R; ++u) intra[u] += pair_energy<true, STRIDE>(F, lane_record<LP>(blk, h, u), my);
+    for (int u = 0; u < R; ++u) intra[u] += pair_energy<true, STRIDE>(F, lane_record<LP, SCALAR>(blk, h, u), my);
   }
   float part[R];
 #pragma unroll

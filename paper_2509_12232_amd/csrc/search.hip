@@ -182,7 +182,9 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   const bool track = S.target != nullptr && S.gen_reached != nullptr;
   const float tgt = track ? S.target[lig] : 0.f;
   auto score = [&](const float *g, int gs) {
-    return score_pose<kStride, LAYOUT, LP>(S.L, S.geom, S.ff, S.maps, H, g, gs, my);
+    // the kernel stores to global memory, so the ligand tables arrive in vector
+    // registers (SCALAR = false)
+    return score_pose<kStride, LAYOUT, LP, 1, false>(S.L, S.geom, S.ff, S.maps, H, g, gs, my);
   };
   for (int c = 0; c < P; c += NT) {
     const int i = c + t;

@@ -295,9 +295,13 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
 
 // Persistent: each workgroup keeps taking ligands from the queue until none is
 // left.  Wavefront w of the group keeps its poses' coordinates in its own LDS
-// region of lds_atoms * 3 rows of 64 / LP dwords.
+// region of lds_atoms * 3 rows of 64 / LP dwords.  With the line layouts the
+// register budget is that of three wavefronts per SIMD (168 VGPRs, against
+// 172-217 unbounded): what does not fit is reloaded once per ligand, generation
+// or scoring pass, never inside a pose.  The other layouts keep two.
 template <int LAYOUT, int LP>
-__global__ __launch_bounds__(kSearchMaxThreads, 2) void search_kernel(SearchLaunch S) {
+__global__ __launch_bounds__(kSearchMaxThreads, (LAYOUT == kQuadLine || LAYOUT == kPairLine) ? 3 : 2) void
+search_kernel(SearchLaunch S) {
   constexpr int kStride = kWave / LP;
   extern __shared__ float lds[];
   __shared__ int s_q;

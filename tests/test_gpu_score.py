@@ -236,6 +236,30 @@ def test_lanes_per_pose_same_bits(dk, ora):
         dk.dock_score_set_lanes_per_pose(3)
 
 
+def test_automatic_lanes_per_pose_follow_layout_and_size(dk):
+    """The automatic scoring shape depends on the set's largest ligand and the
+    pocket's map layout: with pair-line maps two lanes up to 40 atoms and four
+    above; with the other layouts one lane up to 32 atoms, two up to 40, four
+    above.  A fixed setting overrides it and 0 restores it."""
+    ff, rec, grid, maps = system(0)
+    cases = {dk.DOCK_LAYOUT_PAIRLINE: {24: 2, 40: 2, 41: 4, 96: 4},
+             dk.DOCK_LAYOUT_QUADLINE: {24: 1, 32: 1, 40: 2, 41: 4},
+             dk.DOCK_LAYOUT_ZPAIR: {32: 1, 33: 2, 48: 4}}
+    dk.dock_score_set_lanes_per_pose(0)
+    for layout, by_size in cases.items():
+        pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
+        for atoms, want in by_size.items():
+            ligs = dk.dock_create_ligands(pocket, [synth.make_ligand(1, 900 + atoms, 12, 2, 8),
+                                                   synth.make_ligand(1, atoms, atoms, 4, 8)])
+            assert dk.dock_score_lanes_per_pose(ligs) == want, (layout, atoms)
+    try:
+        dk.dock_score_set_lanes_per_pose(1)
+        assert dk.dock_score_lanes_per_pose(ligs) == 1
+    finally:
+        dk.dock_score_set_lanes_per_pose(0)
+    assert dk.dock_score_lanes_per_pose(ligs) == 4
+
+
 def test_max_torsions_and_types(dk, ora):
     """The limits of the ABI at once: 32 atom types (34 maps) and a ligand with
     32 torsions (39 genes), for every map layout and lanes-per-pose shape, plus

@@ -82,13 +82,20 @@ def setup(n_poses: int, seed: int = 1):
                 n_pairs=ligs.pair_count(0))
 
 
+def _code_only(text: str) -> str:
+    """C++ source without // comments, trailing blanks and empty lines (the
+    kernel sources hold no string literal with //)."""
+    lines = (line.split("//", 1)[0].rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash() -> str:
-    """Hash of the scoring kernel's sources; HBM traffic figures recorded under
-    profiles/ are used only while it matches."""
+    """Hash of the scoring kernel's code (its sources less comments); HBM
+    traffic figures recorded under profiles/ are used only while it matches."""
     h = hashlib.sha256()
     for f in ("score.hip", "score_pose.h", "dock_internal.h"):
-        with open(os.path.join(ROOT, "paper_2509_12232_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_12232_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -4,8 +4,8 @@
 //
 // Mapping: a lane (or LP = 2 or 4 lanes, one in each half or quarter of the
 // wavefront) owns a pose.  All ligand data (atoms, torsions, pairs) is uniform
-// across the wavefront and arrives through scalar loads, so every loop below is
-// a scalar loop.  The pose's atom coordinates live in an LDS column: coordinate
+// across the wavefront (in the scoring kernel it arrives through scalar loads),
+// so every loop below is a scalar loop.  The pose's atom coordinates live in an LDS column: coordinate
 // c of atom i at my[(3 i + c) * STRIDE], STRIDE = poses sharing one LDS row, so
 // the lanes that read the same atom hit consecutive dwords.
 #pragma once

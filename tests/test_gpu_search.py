@@ -375,7 +375,7 @@ def test_search_population_extremes(dk, ora, pop):
 
 
 def test_handles_release_device_memory(dk):
-    """Pockets (with their quad-line copy), ligand sets (with side streams),
+    """Pockets (with their packed map copy), ligand sets (with side streams),
     search plans and networks give back their device memory when destroyed:
     twenty create/use/destroy cycles leave free memory where one cycle left it."""
     import gc

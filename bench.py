@@ -266,8 +266,9 @@ def batch_setup(cfg_id: int, extra_cfg: int | None = None):
 
 def search_throughput(B, gens: int, pop: int):
     """One plain search over the whole batch (fresh population, `gens`
-    generations) after the launch-shape autotuner and a 2-generation warm-up:
-    poses scored per second of wall time (pop x (gens + 1) poses per ligand)."""
+    generations) after the launch-shape autotuner and one untimed search of the
+    same length (scratch pool sized, clocks up after the host-side legs): poses
+    scored per second of wall time (pop x (gens + 1) poses per ligand)."""
     import torch
     from paper_2509_12232_amd import proposal as pr
     dk = B["dk"]
@@ -277,9 +278,9 @@ def search_throughput(B, gens: int, pop: int):
     t0 = time.perf_counter()
     dk.dock_search_autotune(B["pocket"], L, p, B["stride"], tune_generations=3)
     tune_s = time.perf_counter() - t0
+    p = dk.SearchParams(pop_size=pop, n_generations=gens, seed=1, box_lo=B["lo"], box_hi=B["hi"])
     dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
     torch.cuda.synchronize()
-    p = dk.SearchParams(pop_size=pop, n_generations=gens, seed=1, box_lo=B["lo"], box_hi=B["hi"])
     t0 = time.perf_counter()
     dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
     torch.cuda.synchronize()

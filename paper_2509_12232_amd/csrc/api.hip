@@ -608,10 +608,12 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
       return hdr[x].n_atoms + pair_count[x] > hdr[y].n_atoms + pair_count[y];
     });
     int mx = 1;
-    for (int32_t l : ids) mx = std::max(mx, hdr[l].n_atoms);
+    int64_t cost = 0;
+    for (int32_t l : ids) mx = std::max(mx, hdr[l].n_atoms), cost += hdr[l].n_atoms + pair_count[l];
     // default shape (until tuned or set): two lanes per pose once the LDS of a
     // lane's coordinates limits residency
-    L->buckets.push_back(LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size(), mx > 16 ? 2 : 1, 0, 0});
+    L->buckets.push_back(
+        LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size(), mx > 16 ? 2 : 1, 0, 0, cost});
     order.insert(order.end(), ids.begin(), ids.end());
     lo = ub;
   }
@@ -818,6 +820,8 @@ static SearchShape bucket_shape(const dock_pocket *p, const LigandBucket &B, int
 // [S.p.first_gen, S.p.first_gen + S.p.n_gen): the buckets run concurrently on the
 // handle's side streams (forked from and joined back to s), so that small
 // buckets do not leave the GPU idle while the last ligands of another finish.
+// Costliest bucket first, each onto the side stream with the least work so far,
+// so the longest bucket never waits behind another.
 static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, SearchLaunch S, int32_t *queues,
                               hipStream_t s, const char **step) {
   const int nb = (int)L->buckets.size();
@@ -829,11 +833,18 @@ static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, Searc
   std::vector<hipEvent_t> joins;
   if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(fork, s);
-  int k = 0;
-  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+  std::vector<int> by_cost;
+  for (int b = 0; b < nb; ++b)
+    if (L->buckets[b].count > 0) by_cost.push_back(b);
+  std::stable_sort(by_cost.begin(), by_cost.end(),
+                   [&](int x, int y) { return L->buckets[x].cost > L->buckets[y].cost; });
+  std::vector<int64_t> load(L->side.size(), 0);
+  for (int b : by_cost) {
+    if (e != hipSuccess) break;
     const LigandBucket &B = L->buckets[b];
-    if (B.count == 0) continue;
-    hipStream_t side = L->side[k++ % L->side.size()];
+    const size_t k = std::min_element(load.begin(), load.end()) - load.begin();
+    load[k] += B.cost;
+    hipStream_t side = L->side[k];
     *step = "side streams";
     e = hipStreamWaitEvent(side, fork, 0);
     S.order = L->order + B.offset;

@@ -1,0 +1,34 @@
+"""Host logic of bench.py: the committed HBM traffic record applies only to the
+scoring kernel's code it was measured on, and only to its workload."""
+import bench
+
+
+def test_code_only_ignores_comments_and_blank_lines():
+    a = "int x = 1;  // one\n\n// a comment line\nfloat y = 2.f;\n"
+    b = "int x = 1;\n  // reworded comment\nfloat y = 2.f;   \n\n"
+    c = "int x = 2;\nfloat y = 2.f;\n"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(c)
+    assert bench._code_only(a) == "int x = 1;\nfloat y = 2.f;"
+
+
+def _recorded_hash():
+    import os
+    path = os.path.join(bench.ROOT, "profiles", "score_kernel_config1_traffic.txt")
+    for line in open(path):
+        if line.startswith("kernel_hash"):
+            return line.split("=", 1)[1].strip()
+    raise AssertionError("no kernel_hash in the traffic record")
+
+
+def test_recorded_traffic_applies_to_its_workload_only(monkeypatch):
+    # as if the kernel code were the one the record was taken on
+    monkeypatch.setattr(bench, "kernel_source_hash", _recorded_hash)
+    t = bench.recorded_traffic(10_000_000)
+    assert t is not None and t > 0
+    assert bench.recorded_traffic(9_999_999) is None
+
+
+def test_recorded_traffic_refuses_a_changed_kernel(monkeypatch):
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.recorded_traffic(10_000_000) is None

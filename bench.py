@@ -295,7 +295,7 @@ def search_throughput(B, gens: int, pop: int):
     torch.cuda.synchronize()
     graph_dt = time.perf_counter() - t0
     del plan
-    shapes = {f"<={b}": {"lanes_per_pose": lp, "waves": w} for b, lp, w in dk.dock_search_shapes(L)}
+    shapes = {f"<={b}": {"split": ws, "blocks": nb} for b, ws, nb in dk.dock_search_shapes(L)}
     return {"ligands": L.n, "pop": pop, "generations": gens, "seconds": round(dt, 4),
             "graph_seconds": round(graph_dt, 4), "graph_poses_per_s": round(n / graph_dt, 1),
             "poses_per_s": round(n / dt, 1), "best_median": round(float(buf["be"].median()), 4),
@@ -361,7 +361,10 @@ def learned_vs_plain():
     """Time-to-target on the 10000-ligand batch, plain DE vs the learned proposal.
 
     The network is trained (on the GPU, by the library's kernels) on plain runs
-    over 5000 other ligands.  Batch level: GPU time until the median best energy
+    over 5000 other ligands.  A control runs the same proposal rounds from the
+    untrained network (its seeded initial weights), so that what training
+    itself buys is measured apart from what the extra exactly scored proposals
+    buy.  Batch level: GPU time until the median best energy
     over the batch reaches the plain search's final median + 0.1 kcal/mol.
     Ligand level: the fraction of ligands whose best reaches the plain (seed 1)
     final best + 0.1, and the generations it took; a plain run with another
@@ -398,15 +401,22 @@ def learned_vs_plain():
     del x, t
     prop = pr.ProposalConfig()
     learned_pts, lbuf = pr.anytime(B["pocket"], L_ev, P, stride, net, prop, reference_best=ref_best)
+    # the control: the same proposal rounds from the same network before training
+    # (its initial weights, seeded as the trained one's were)
+    net0 = dk.dock_mlp_create(0, cfg.seed)
+    untrained_pts, _ = pr.anytime(B["pocket"], L_ev, P, stride, net0, prop, reference_best=ref_best)
     from dataclasses import replace
     plain2_pts, buf2 = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, reference_best=ref_best)
     # the same comparison with seed 2 on both sides (its own plain level)
     level2 = float(np.median(buf2["be"].cpu().numpy())) + 0.1
     learned2_pts, _ = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, net, prop, reference_best=ref_best)
+    untrained2_pts, _ = pr.anytime(B["pocket"], L_ev, replace(P, seed=2), stride, net0, prop,
+                                   reference_best=ref_best)
     # ligand level, with every ligand stopping at its target
     stops = {"plain_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target),
              "plain_seed2": pr.time_to_target(B["pocket"], L_ev, replace(P, seed=2), stride, target),
-             "learned_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target, net, prop)}
+             "learned_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target, net, prop),
+             "untrained_seed1": pr.time_to_target(B["pocket"], L_ev, P, stride, target, net0, prop)}
 
     def lig_stats(r):
         g = r["gen_reached"]
@@ -420,22 +430,30 @@ def learned_vs_plain():
     t2_ms, t2_gen = pr.time_to_level(plain2_pts, level)
     s2_plain, _ = pr.time_to_level(plain2_pts, level2)
     s2_learned, s2_gen = pr.time_to_level(learned2_pts, level2)
+    tu_ms, tu_gen = pr.time_to_level(untrained_pts, level)
+    s2_untrained, _ = pr.time_to_level(untrained2_pts, level2)
     rnd = (lambda v: None if v is None else round(v, 1))
+    ratio = (lambda a, b: round(a / b, 3) if a and b else None)
     return {
         "workload": f"{L_ev.n} ligands (atoms lognormal median 32, 8-96; 0-20 torsions), 14 fp32 maps at 80^3, "
                     f"DE pop {P.pop_size} x {P.n_generations} generations",
         "level": round(level, 4),
-        "batch_time_to_level_ms": {"plain_seed1": rnd(tp_ms), "plain_seed2": rnd(t2_ms), "learned_seed1": rnd(tl_ms)},
+        "batch_time_to_level_ms": {"plain_seed1": rnd(tp_ms), "plain_seed2": rnd(t2_ms), "learned_seed1": rnd(tl_ms),
+                                   "untrained_seed1": rnd(tu_ms)},
         "batch_generations_to_level": {"plain_seed1": rnd(tp_gen), "plain_seed2": rnd(t2_gen),
-                                       "learned_seed1": rnd(tl_gen)},
-        "speedup_vs_plain_seed1": round(tp_ms / tl_ms, 3) if tp_ms and tl_ms else None,
+                                       "learned_seed1": rnd(tl_gen), "untrained_seed1": rnd(tu_gen)},
+        "speedup_vs_plain_seed1": ratio(tp_ms, tl_ms),
+        # what training buys: the same rounds from the untrained network against the trained one
+        "speedup_trained_vs_untrained": {"seed1": ratio(tu_ms, tl_ms), "seed2": ratio(s2_untrained, s2_learned)},
         "seed2": {"level": round(level2, 4), "plain_ms": rnd(s2_plain), "learned_ms": rnd(s2_learned),
-                  "learned_generations": rnd(s2_gen),
-                  "speedup": round(s2_plain / s2_learned, 3) if s2_plain and s2_learned else None},
+                  "untrained_ms": rnd(s2_untrained), "learned_generations": rnd(s2_gen),
+                  "speedup": ratio(s2_plain, s2_learned)},
         "median_best_at_end": {"plain_seed1": round(plain_pts[-1][2], 4), "plain_seed2": round(plain2_pts[-1][2], 4),
-                               "learned_seed1": round(learned_pts[-1][2], 4)},
+                               "learned_seed1": round(learned_pts[-1][2], 4),
+                               "untrained_seed1": round(untrained_pts[-1][2], 4)},
         "gpu_ms_at_end": {"plain_seed1": round(plain_pts[-1][1], 1), "plain_seed2": round(plain2_pts[-1][1], 1),
-                          "learned_seed1": round(learned_pts[-1][1], 1)},
+                          "learned_seed1": round(learned_pts[-1][1], 1),
+                          "untrained_seed1": round(untrained_pts[-1][1], 1)},
         "ligand_targets": {k: lig_stats(v) for k, v in stops.items()},
         "proposal": {"step": prop.step, "every": prop.every, "until": prop.until},
         "training": {"ligands": L_tr.n, "tuples_available": n_tuples_avail, "tuples": cfg.n_tuples,
@@ -489,6 +507,27 @@ def schedule_sweep(seeds=(1, 2)):
                                   for (a, e, u), v in rank[:10]]}), flush=True)
 
 
+def profile_search(gens: int = 30):
+    """Short searches over the 10000-ligand batch for counter runs: the
+    autotuner, then two plain searches of `gens` generations from a fresh
+    population (the second one is the one to read)."""
+    import torch
+    from paper_2509_12232_amd import proposal as pr
+    B = batch_setup(3)
+    dk = B["dk"]
+    L = B["handles"][0]
+    c = B["c"]
+    buf = pr._buffers(L.n, c["pop"], B["stride"])
+    p = dk.SearchParams(pop_size=c["pop"], n_generations=gens, seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    dk.dock_search_autotune(B["pocket"], L, p, B["stride"], tune_generations=3)
+    shapes = {f"<={b}": (lp, w) for b, lp, w in dk.dock_search_shapes(L)}
+    for k in range(2):
+        t0 = time.perf_counter()
+        dk.dock_search(B["pocket"], L, p, buf["pop"], buf["pe"], buf["bg"], buf["be"])
+        torch.cuda.synchronize()
+        log(f"search {k}: {gens} generations in {time.perf_counter() - t0:.3f} s, shapes {shapes}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -501,6 +540,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="for rocprofv3 counter runs: one 1 GiB device copy (calibration of the "
                          "FETCH_SIZE/WRITE_SIZE counters) and two scoring steps, nothing else")
+    ap.add_argument("--profile-search", action="store_true",
+                    help="for rocprofv3 runs of the search kernel: the 10000-ligand batch, the launch-shape "
+                         "autotuner, then two plain searches of 30 generations, nothing else")
     ap.add_argument("--schedule-sweep", action="store_true",
                     help="choose the learned proposal's round schedule on the validation batch, nothing else")
     args = ap.parse_args()
@@ -514,6 +556,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     if args.schedule_sweep:
         schedule_sweep()
+        return
+    if args.profile_search:
+        profile_search()
         return
     S = setup(args.poses)
     dk = S["dk"]
@@ -565,7 +610,7 @@ def main():
                 "traffic_GBs": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
                 "traffic_frac": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
-                "lanes_per_pose": S["dk"].dock_score_lanes_per_pose(S["ligs"]),
+                "split": S["dk"].dock_score_split(S["ligs"]),
                 "kernel_ms_sd": round(float(np.std(step_ms)), 4), "kernel_ms_min": round(float(np.min(step_ms)), 4),
                 "alu": {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},

@@ -157,16 +157,17 @@ typedef struct {
   const float *xyz;             /* [n_atoms][3] reference conformation */
   const int32_t *type;          /* [n_atoms] in [0, n_types) */
   const float *charge;          /* [n_atoms] */
-  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree (a ring makes it DOCK_E_INVALID) */
+  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree: a ring is DOCK_E_UNSUPPORTED */
   const int32_t *torsion_bonds; /* [n_torsions] distinct indices into bonds, neither end of degree 1 */
 } dock_ligand_desc;
 
 /* Preprocess a ligand set for a pocket: root at atom 0, ligand origin at the
  * centroid of the reference conformation, intra pairs = atom pairs at least four
  * bonds apart that lie in different rigid fragments (Algorithm 2's pair loop; no
- * distance cutoff).  Errors: DOCK_E_INVALID (bonds not a tree, torsion on a
- * terminal or repeated bond, type out of range, non-finite input, n_ligands < 1),
- * DOCK_E_UNSUPPORTED (> 96 atoms, > 32 torsions), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+ * distance cutoff).  Errors: DOCK_E_INVALID (bonds out of range or not
+ * connecting all atoms, torsion on a terminal or repeated bond, type out of
+ * range, non-finite input, n_ligands < 1), DOCK_E_UNSUPPORTED (> 96 atoms, > 32
+ * torsions, bonds that close a ring), DOCK_E_NOMEM, DOCK_E_DEVICE. */
 dock_status dock_create_ligands(const dock_pocket *pocket, const dock_ligand_desc *ligands,
                                 int32_t n_ligands, dock_ligands **out);
 
@@ -192,19 +193,17 @@ dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs
                              int64_t n_poses, float *energies, void *stream);
 
 /* Launch shape of dock_score_poses (a tuning knob; energies are bit-identical
- * for every shape): lanes_per_pose = 1, 2 or 4 lanes build and score one pose
- * together, a wavefront then holds 64 / lanes_per_pose poses and needs
- * 1 / lanes_per_pose of the LDS, so more wavefronts stay resident for large
- * ligands; 0 restores the automatic choice by the set's largest ligand and the
- * pocket's map layout.  Process-wide; takes effect at the next call.  Errors: DOCK_E_INVALID for any
- * other value. */
-dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose);
+ * for every shape).  Poses are scored in blocks of 64, one per lane; split =
+ * 1, 2 or 4 wavefronts build and score a block together, sharing its LDS (3
+ * floats per atom per pose) and splitting each pose's atoms and pair records,
+ * so more wavefronts stay resident for large ligands; 0 restores the automatic
+ * choice by the set's largest ligand.  Process-wide; takes effect at the next
+ * call.  Errors: DOCK_E_INVALID for any other value. */
+dock_status dock_score_set_split(int32_t split);
 
-/* The lanes per pose dock_score_poses uses for ligand set ligs with the pocket
- * it was created for (the setting above, or the automatic choice, which depends
- * on the set's largest ligand and the pocket's map layout).  Errors:
- * DOCK_E_INVALID (null argument). */
-dock_status dock_score_lanes_per_pose(const dock_ligands *ligs, int32_t *lanes_per_pose);
+/* The split dock_score_poses uses for ligand set ligs (the setting above, or
+ * the automatic choice).  Errors: DOCK_E_INVALID (null argument). */
+dock_status dock_score_split(const dock_ligands *ligs, int32_t *split);
 
 /* Differential evolution (DE/rand/1/bin, greedy selection) as the evolutionary
  * search of Sec. V.  Random draws come from Philox4x64-10 (Salmon et al., SC'11)
@@ -289,20 +288,20 @@ dock_status dock_search_plan_destroy(dock_search_plan *plan);
 
 /* ---- Launch shapes of the search and their autotuner --------------------------
  * dock_search runs one persistent kernel per ligand-size bucket (atom counts
- * up to 16, 32, 48, 64, 96).  Its shape: lanes per pose (1: each lane builds
- * and scores a pose; 2 or 4: that many lanes share a pose, splitting its atoms
- * and pair records, which divides the LDS per wavefront by as much) and
- * wavefronts per workgroup (1-4, 0 = chosen at launch from the ligand count and
- * the LDS residency).  Energies, and hence search results, do not depend on
- * the shape: every form sums the
- * same partial sums in the same order.  Shapes are launch configuration kept in
+ * up to 16, 32, 48, 64, 96); a workgroup runs one ligand's search at a time.
+ * Its shape: the split (1, 2 or 4 wavefronts build and score a block of 64
+ * individuals together, splitting their atoms and pair records and sharing
+ * the block's LDS) and blocks per workgroup (1 up to 12 / split, 0 = chosen at
+ * launch from the ligand count and the LDS residency).  Energies, and hence
+ * search results, do not depend on the shape: every form sums the same
+ * partial sums in the same order.  Shapes are launch configuration kept in
  * the ligand handle (the one exception to its immutability): set or tune them
  * while no search on the handle is in flight. */
 #define DOCK_SEARCH_BUCKETS 5
 typedef struct {
   int32_t max_atoms;        /* the bucket's upper atom count (read-only: 16, 32, 48, 64, 96) */
-  int32_t lanes_per_pose;   /* 1, 2 or 4 */
-  int32_t waves_per_group;  /* 0..4 */
+  int32_t split;            /* wavefronts per block of 64 individuals: 1, 2 or 4 */
+  int32_t blocks_per_group; /* 0..12 / split */
 } dock_search_shape;
 
 /* The handle's shapes, host dock_search_shape[DOCK_SEARCH_BUCKETS]: the
@@ -314,7 +313,8 @@ dock_status dock_search_shapes(const dock_ligands *ligs, dock_search_shape *shap
 dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *shapes);
 /* Autotuner: for every non-empty bucket, times a search of tune_generations
  * generations (params' pop_size, seed, box) of the bucket's ligands for every
- * shape (1, 2 and 4 lanes per pose x 1 up to 4 wavefronts), warm-up run first,
+ * shape (split 1, 2 and 4 x 1 up to 12 / split blocks, at most one block per
+ * 64 individuals), warm-up run first,
  * with HIP events on stream, and fixes the fastest.  Results are cached for the
  * process under (device architecture and compute-unit count, map layout and
  * dimensions, bucket, its largest ligand, pop_size); a cached bucket is not
@@ -328,8 +328,8 @@ dock_status dock_search_autotune(const dock_pocket *pocket, dock_ligands *ligs, 
  * same architecture and compute-unit count) uses tuned shapes without timing
  * them again.  dock_search_tune_save writes every cached shape of this process
  * to the text file at path (a header line, then one line per shape: arch n_cu
- * layout nx ny nz n_types bucket_upper largest_ligand pop lanes_per_pose
- * waves_per_group), replacing the file.  dock_search_tune_load reads such a
+ * layout nx ny nz n_types bucket_upper largest_ligand pop split
+ * blocks_per_group), replacing the file.  dock_search_tune_load reads such a
  * file and merges it into this process's cache (an entry with the same key is
  * replaced); if any line is malformed or out of range nothing is loaded.
  * Host-only; no device is touched.  Errors: DOCK_E_INVALID (null path, the

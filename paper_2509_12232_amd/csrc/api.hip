@@ -69,7 +69,7 @@ hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s) {
   }
   return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
-extern "C" int32_t dock_version(void) { return 1; }
+extern "C" int32_t dock_version(void) { return 2; }
 
 // ------------------------------------------------------------------------------ handles
 // Packed layout for the scoring kernel: the pair-line layout (one cache line
@@ -422,7 +422,7 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
       for (int k = (int)adj[u].size() - 1; k >= 0; --k) {
         const int v = adj[u][k];
         if (v == parent[u]) continue;
-        if (seen[v]) return set_err(DOCK_E_INVALID, "ligand %d: bonds do not form a tree (rings are not supported)", lig);
+        if (seen[v]) return set_err(DOCK_E_UNSUPPORTED, "ligand %d: the bonds close a ring (rings are not supported)", lig);
         seen[v] = 1;
         parent[v] = u;
         stack.push_back(v);
@@ -610,10 +610,10 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
     int mx = 1;
     int64_t cost = 0;
     for (int32_t l : ids) mx = std::max(mx, hdr[l].n_atoms), cost += hdr[l].n_atoms + pair_count[l];
-    // default shape (until tuned or set): two lanes per pose once the LDS of a
-    // lane's coordinates limits residency
+    // default shape (until tuned or set): blocks split over four wavefronts once
+    // the LDS of their coordinates limits residency
     L->buckets.push_back(
-        LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size(), mx > 16 ? 2 : 1, 0, 0, cost});
+        LigandBucket{ub, mx, (int32_t)order.size(), (int32_t)ids.size(), mx > 16 ? 4 : 1, 0, 0, cost});
     order.insert(order.end(), ids.begin(), ids.end());
     lo = ub;
   }
@@ -647,39 +647,39 @@ extern "C" dock_status dock_destroy_ligands(dock_ligands *L) {
 }
 
 // ------------------------------------------------------------------------------ scoring
-// Lanes per pose of the scoring kernel: 0 = automatic (score_lanes_auto).
-static std::atomic<int32_t> g_score_lanes{0};
+// Split of the scoring kernel (wavefronts per block of 64 poses): 0 = automatic
+// (score_split_auto).
+static std::atomic<int32_t> g_score_split{0};
 
-// Automatic shape, from measurements on MI355X (fourteen 100^3 maps, 4e6 random
-// poses of one ligand of each size).  The one-lane wavefront's LDS (3 floats per
-// atom per pose) leaves five wavefronts per CU at 40 atoms; more lanes split the
-// pair terms.  With the pair-line maps two lanes are fastest from 12 to 40 atoms
-// (+16% over one at 32 atoms, +7% over four at 40), four above (+8% over two at
-// 48 atoms, +17% at 64, +41% at 96).  With the other layouts, whose lookups take
-// longer: up to 32 atoms the three shapes are within 1%, at 40 two lanes are
-// fastest (+16% over one), above that four.
-static int32_t score_lanes_auto(int32_t max_atoms, int32_t layout) {
-  if (layout == kPairLine) return max_atoms <= 40 ? 2 : 4;
-  if (max_atoms <= 32) return 1;
-  if (max_atoms <= 40) return 2;
+// Automatic split.  A block's LDS (3 floats per atom per pose, 64 poses) is
+// shared by its wavefronts, so a larger split keeps more wavefronts resident
+// per CU for the same LDS, at the cost of the pose build's barriers and of the
+// per-torsion setup each wavefront repeats.  Measured on MI355X (fourteen
+// 100^3 maps in the pair-line layout, 4e6 random poses of one ligand of each
+// size), four wavefronts were the fastest at every size from 12 to 96 atoms:
+// within 3% of one up to 24 atoms, then 1.39x (32 atoms), 1.67x (40), 1.93x
+// (48), 2.06x (64) and 2.20x (96) faster than one.
+static int32_t score_split_auto(int32_t max_atoms, int32_t layout) {
+  (void)max_atoms;
+  (void)layout;
   return 4;
 }
 
-static int32_t score_lanes(const dock_ligands *L, int32_t layout) {
-  const int32_t lp = g_score_lanes.load();
-  return lp ? lp : score_lanes_auto(L->max_atoms, layout);
+static int32_t score_split(const dock_ligands *L, int32_t layout) {
+  const int32_t ws = g_score_split.load();
+  return ws ? ws : score_split_auto(L->max_atoms, layout);
 }
 
-extern "C" dock_status dock_score_set_lanes_per_pose(int32_t lanes_per_pose) {
-  if (lanes_per_pose != 0 && lanes_per_pose != 1 && lanes_per_pose != 2 && lanes_per_pose != 4)
-    return set_err(DOCK_E_INVALID, "lanes_per_pose must be 0, 1, 2 or 4");
-  g_score_lanes.store(lanes_per_pose);
+extern "C" dock_status dock_score_set_split(int32_t split) {
+  if (split != 0 && split != 1 && split != 2 && split != 4)
+    return set_err(DOCK_E_INVALID, "split must be 0, 1, 2 or 4");
+  g_score_split.store(split);
   return DOCK_OK;
 }
 
-extern "C" dock_status dock_score_lanes_per_pose(const dock_ligands *L, int32_t *lanes_per_pose) {
-  if (!L || !lanes_per_pose) return set_err(DOCK_E_INVALID, "null argument");
-  *lanes_per_pose = score_lanes(L, L->layout);
+extern "C" dock_status dock_score_split(const dock_ligands *L, int32_t *split) {
+  if (!L || !split) return set_err(DOCK_E_INVALID, "null argument");
+  *split = score_split(L, L->layout);
   return DOCK_OK;
 }
 
@@ -691,7 +691,7 @@ static ScoreLaunch make_score(const dock_pocket *p, const dock_ligands *L) {
   a.maps = p->view();
   a.layout = p->layout;
   a.lds_atoms = L->max_atoms;
-  a.lanes_per_pose = score_lanes(L, p->layout);
+  a.split = score_split(L, p->layout);
   return a;
 }
 
@@ -800,8 +800,8 @@ ShapeKey shape_key(const dock_pocket *p, const LigandBucket &B, int pop) {
                   B.upper, B.lds_atoms, pop};
 }
 
-constexpr const char *kTuneHeader = "# dock search shapes v1: arch n_cu layout nx ny nz n_types bucket_upper "
-                                    "largest_ligand pop lanes_per_pose waves_per_group";
+constexpr const char *kTuneHeader = "# dock search shapes v2: arch n_cu layout nx ny nz n_types bucket_upper "
+                                    "largest_ligand pop split blocks_per_group";
 
 }  // namespace
 
@@ -813,7 +813,7 @@ static SearchShape bucket_shape(const dock_pocket *p, const LigandBucket &B, int
     auto it = g_shapes.find(shape_key(p, B, pop));
     if (it != g_shapes.end()) return it->second;
   }
-  return SearchShape{B.lanes_per_pose, B.waves};
+  return SearchShape{B.split, B.blocks};
 }
 
 // One pass of the persistent search kernels over every size bucket, generations
@@ -1078,7 +1078,7 @@ extern "C" dock_status dock_search_plan_destroy(dock_search_plan *P) {
 extern "C" dock_status dock_search_shapes(const dock_ligands *L, dock_search_shape *shapes) {
   if (!L || !shapes) return set_err(DOCK_E_INVALID, "null argument");
   for (size_t b = 0; b < L->buckets.size(); ++b)
-    shapes[b] = dock_search_shape{L->buckets[b].upper, L->buckets[b].lanes_per_pose, L->buckets[b].waves};
+    shapes[b] = dock_search_shape{L->buckets[b].upper, L->buckets[b].split, L->buckets[b].blocks};
   return DOCK_OK;
 }
 
@@ -1087,15 +1087,15 @@ extern "C" dock_status dock_search_set_shapes(dock_ligands *L, const dock_search
   for (size_t b = 0; b < L->buckets.size(); ++b) {
     const dock_search_shape &x = shapes[b];
     if (x.max_atoms != L->buckets[b].upper) return set_err(DOCK_E_INVALID, "bucket %d bound must be %d", (int)b, L->buckets[b].upper);
-    if (x.lanes_per_pose != 1 && x.lanes_per_pose != 2 && x.lanes_per_pose != 4)
-      return set_err(DOCK_E_INVALID, "lanes_per_pose must be 1, 2 or 4");
-    if (x.waves_per_group < 0 || x.waves_per_group > kSearchMaxThreads / kWave)
-      return set_err(DOCK_E_INVALID, "waves_per_group must be in 0..%d", kSearchMaxThreads / kWave);
+    if (x.split != 1 && x.split != 2 && x.split != 4) return set_err(DOCK_E_INVALID, "split must be 1, 2 or 4");
+    if (x.blocks_per_group < 0 || x.blocks_per_group * x.split * kWave > kSearchMaxThreads)
+      return set_err(DOCK_E_INVALID, "blocks_per_group must be in 0..%d for split %d",
+                     kSearchMaxThreads / (kWave * x.split), x.split);
   }
   std::lock_guard<std::mutex> guard(L->side_mu);
   for (size_t b = 0; b < L->buckets.size(); ++b) {
-    L->buckets[b].lanes_per_pose = shapes[b].lanes_per_pose;
-    L->buckets[b].waves = shapes[b].waves_per_group;
+    L->buckets[b].split = shapes[b].split;
+    L->buckets[b].blocks = shapes[b].blocks_per_group;
     L->buckets[b].fixed = 1;
   }
   return DOCK_OK;
@@ -1149,7 +1149,7 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
       auto it = g_shapes.find(shape_key(p, B, P));
       if (it != g_shapes.end()) {
         std::lock_guard<std::mutex> guard(L->side_mu);
-        B.lanes_per_pose = it->second.lanes_per_pose, B.waves = it->second.waves, B.fixed = 1;
+        B.split = it->second.split, B.blocks = it->second.blocks, B.fixed = 1;
         continue;
       }
     }
@@ -1159,10 +1159,10 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
     S.lds_atoms = B.lds_atoms;
     SearchShape best{0, 0};
     float best_ms = 0.f;
-    for (int lp = 1; lp <= 4 && e == hipSuccess; lp *= 2) {
-      const int max_w = std::min(kSearchMaxThreads / kWave, (P * lp + kWave - 1) / kWave);
-      for (int w = 1; w <= max_w && e == hipSuccess; ++w) {
-        const SearchShape shape{lp, w};
+    for (int ws = 1; ws <= 4 && e == hipSuccess; ws *= 2) {
+      const int max_b = std::min(kSearchMaxThreads / (kWave * ws), (P + kBlock - 1) / kBlock);
+      for (int nb = 1; nb <= max_b && e == hipSuccess; ++nb) {
+        const SearchShape shape{ws, nb};
         if (!search_shape_fits(B.lds_atoms, shape)) continue;
         float ms = 0.f;
         // a warm-up run, then the timed one
@@ -1181,14 +1181,14 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
           if (e == hipSuccess) e = hipEventSynchronize(t1);
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
         }
-        if (e == hipSuccess && ms >= 0.f && (best.lanes_per_pose == 0 || ms < best_ms)) best = shape, best_ms = ms;
+        if (e == hipSuccess && ms >= 0.f && (best.split == 0 || ms < best_ms)) best = shape, best_ms = ms;
       }
     }
-    if (e != hipSuccess || best.lanes_per_pose == 0) break;
+    if (e != hipSuccess || best.split == 0) break;
     {
       std::lock_guard<std::mutex> guard(L->side_mu);
-      B.lanes_per_pose = best.lanes_per_pose;
-      B.waves = best.waves;
+      B.split = best.split;
+      B.blocks = best.blocks;
       B.fixed = 1;
     }
     std::lock_guard<std::mutex> g(g_shape_mu);
@@ -1212,7 +1212,7 @@ extern "C" dock_status dock_search_tune_save(const char *path) {
     for (const auto &kv : g_shapes) {
       const ShapeKey &k = kv.first;
       snprintf(line, sizeof line, "%s %d %d %d %d %d %d %d %d %d %d %d\n", k.arch.c_str(), k.n_cu, k.layout, k.nx,
-               k.ny, k.nz, k.n_types, k.upper, k.lds_atoms, k.pop, kv.second.lanes_per_pose, kv.second.waves);
+               k.ny, k.nz, k.n_types, k.upper, k.lds_atoms, k.pop, kv.second.split, kv.second.blocks);
       text += line;
     }
   }
@@ -1240,12 +1240,12 @@ extern "C" dock_status dock_search_tune_load(const char *path) {
     SearchShape sh{};
     char extra[2];
     const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %1s", arch, &k.n_cu, &k.layout, &k.nx, &k.ny,
-                           &k.nz, &k.n_types, &k.upper, &k.lds_atoms, &k.pop, &sh.lanes_per_pose, &sh.waves, extra);
+                           &k.nz, &k.n_types, &k.upper, &k.lds_atoms, &k.pop, &sh.split, &sh.blocks, extra);
     const bool valid = got == 12 && k.n_cu > 0 && k.layout >= kLinear && k.layout <= kPairLine && k.nx >= 2 &&
                        k.ny >= 2 && k.nz >= 2 && k.n_types >= 1 && k.n_types <= kMaxTypes && k.upper >= 1 &&
                        k.upper <= kMaxAtoms && k.lds_atoms >= 1 && k.lds_atoms <= k.upper && k.pop >= 4 &&
-                       (sh.lanes_per_pose == 1 || sh.lanes_per_pose == 2 || sh.lanes_per_pose == 4) &&
-                       sh.waves >= 0 && sh.waves <= kSearchMaxThreads / kWave;
+                       (sh.split == 1 || sh.split == 2 || sh.split == 4) && sh.blocks >= 0 &&
+                       sh.blocks * sh.split * kWave <= kSearchMaxThreads;
     if (!valid) {
       st = set_err(DOCK_E_INVALID, "%s line %d: not a search shape", path, n_line);
       break;

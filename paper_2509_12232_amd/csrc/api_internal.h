@@ -89,8 +89,8 @@ struct LigandBucket {
   int32_t upper;      // atom-count bound of the bucket
   int32_t lds_atoms;  // largest ligand actually in it (sizes the LDS of its launch)
   int32_t offset, count;
-  int32_t lanes_per_pose;  // launch shape of its search kernel
-  int32_t waves;           // wavefronts per workgroup (0: chosen at launch)
+  int32_t split;           // launch shape of its search kernel: wavefronts per block of 64 poses
+  int32_t blocks;          // blocks per workgroup (0: chosen at launch)
   int32_t fixed;           // 1: shape set by the caller or the autotuner
   int64_t cost;            // sum of atoms + pairs over its ligands (work estimate)
 };

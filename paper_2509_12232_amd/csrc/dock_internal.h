@@ -11,6 +11,7 @@ constexpr int kMaxAtoms = 96;
 constexpr int kMaxTorsions = 32;
 constexpr int kMaxTypes = 32;
 constexpr int kWave = 64;
+constexpr int kBlock = kWave;   // poses per scoring block: one per lane
 
 // Per ligand.  Atoms are renumbered in depth-first pre-order from the root
 // (atom 0), so every rotatable bond's moving fragment is one contiguous range.
@@ -125,7 +126,7 @@ struct ScoreLaunch {
   int64_t n_poses;
   float *energies;
   int32_t lds_atoms;           // atom slots per pose in LDS
-  int32_t lanes_per_pose;      // 1, 2 or 4
+  int32_t split;               // wavefronts per block of 64 poses: 1, 2 or 4
 };
 
 // Launchers (one translation unit per kernel family).

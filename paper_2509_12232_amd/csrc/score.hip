@@ -1,63 +1,77 @@
 // score.hip -- batched pose scoring kernel for gfx950.
 //
-// One 64-lane workgroup (one wavefront) scores 64 / LP poses with LP = 1, 2 or 4
-// lanes per pose (the same bits for every LP).  Poses of one ligand share every
-// uniform load; a wavefront holding poses of several ligands walks them one
-// ligand at a time (each pass masks the other lanes).
+// One workgroup of WS = 1, 2 or 4 wavefronts scores a block of 64 poses, one
+// per lane, the wavefronts splitting each pose's atoms and pair records (the
+// same bits for every WS).  Poses of one ligand share every uniform load; a
+// block holding poses of several ligands scores it once per ligand, each pass
+// keeping the results of its own lanes.
 #include "dock_internal.h"
 #include "score_pose.h"
 
+#include <algorithm>
+
 namespace dock {
 
-template <int LAYOUT, int LP>
-__global__ __launch_bounds__(kWave) void score_kernel(ScoreLaunch A) {
-  constexpr int PPW = kWave / LP;  // poses per wavefront; lane p + PPW h is lane h of pose p
+template <int LAYOUT, int WS>
+__global__ __launch_bounds__(kWave * WS) void score_kernel(ScoreLaunch A, int64_t first) {
   extern __shared__ float lds[];
-  const int lane = threadIdx.x;
-  const int p = lane % PPW;
-  const int64_t pose = (int64_t)blockIdx.x * PPW + p;
-  if (pose >= A.n_poses) return;   // all LP lanes of a pose leave together
-  int lig;
-  if (A.poses_per_ligand > 0) lig = (int)(pose / A.poses_per_ligand);
-  else lig = A.pose_ligand ? A.pose_ligand[pose] : 0;
-  const bool valid = (lig >= 0) & (lig < A.L.n_ligs);
+  const int lane = threadIdx.x % kWave;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t pose = first + (int64_t)blockIdx.x * kBlock + lane;
+  const bool live = pose < A.n_poses;
+  int lig = -1;
+  if (live) {
+    if (A.poses_per_ligand > 0) lig = (int)(pose / A.poses_per_ligand);
+    else lig = A.pose_ligand ? A.pose_ligand[pose] : 0;
+  }
+  const bool valid = live & (lig >= 0) & (lig < A.L.n_ligs);
   float e = __builtin_nanf("");
-  const float *g = A.genotypes + pose * (int64_t)A.g_stride;
-  float *my = lds + p;
+  // lanes past the end read pose 0's genes (in bounds), and their results are dropped
+  const float *g = A.genotypes + (live ? pose : 0) * (int64_t)A.g_stride;
+  float *my = lds + lane;
+  float *red = lds + 3 * A.lds_atoms * kBlock + lane;
+  // the same ligand sequence in every wavefront of the block (the same lanes),
+  // so all of them meet the same barriers
   uint64_t todo = __ballot(valid);
   while (todo) {
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
-    const LigHeader H = A.L.hdr[cur];
-    // map loads two atoms ahead with one or two lanes per pose (measured faster
-    // on MI355X; with four lanes the extra registers cost more than they hide)
-    if (valid && lig == cur) e = score_pose<PPW, LAYOUT, LP, LP <= 2 ? 2 : 1>(A.L, A.geom, A.ff, A.maps, H, g, 1, my);
+    const LigHeader H = as_const(A.L.hdr)[cur];
+    // map loads two atoms ahead with one or two wavefronts per block (measured
+    // faster on MI355X; with four the extra registers cost more than they hide)
+    const float v = score_pose<LAYOUT, WS, WS <= 2 ? 2 : 1>(A.L, A.geom, A.ff, A.maps, H, g, 1, my, red, h);
+    if (valid && lig == cur) e = v;
     todo &= ~__ballot(valid && lig == cur);
   }
-  if (lane < PPW) A.energies[pose] = e;
+  if (h == 0 && live) A.energies[pose] = e;
 }
 
-template <int LAYOUT, int LP>
-static hipError_t launch_score_lp(const ScoreLaunch &a, hipStream_t s) {
-  constexpr int PPW = kWave / LP;
-  const int64_t blocks = (a.n_poses + PPW - 1) / PPW;
-  const size_t lds = (size_t)a.lds_atoms * 3 * PPW * sizeof(float);
+// Poses per launch: the grid's work-items (64 WS per block) stay below 2^31.
+constexpr int64_t kPosesPerLaunch = (int64_t)1 << 24;
+
+template <int LAYOUT, int WS>
+static hipError_t launch_score_ws(const ScoreLaunch &a, hipStream_t s) {
+  const size_t lds = ((size_t)a.lds_atoms * 3 + (WS > 1 ? WS : 0)) * kBlock * sizeof(float);
+  auto fn = score_kernel<LAYOUT, WS>;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)score_kernel<LAYOUT, LP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  auto fn = score_kernel<LAYOUT, LP>;
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kWave), lds, s, a);
-  return hipGetLastError();
+  for (int64_t first = 0; first < a.n_poses; first += kPosesPerLaunch) {
+    const int64_t n = std::min<int64_t>(kPosesPerLaunch, a.n_poses - first);
+    const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kWave * WS), lds, s, a, first);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int LAYOUT>
 static hipError_t launch_score_t(const ScoreLaunch &a, hipStream_t s) {
-  switch (a.lanes_per_pose) {
-    case 1: return launch_score_lp<LAYOUT, 1>(a, s);
-    case 2: return launch_score_lp<LAYOUT, 2>(a, s);
-    case 4: return launch_score_lp<LAYOUT, 4>(a, s);
+  switch (a.split) {
+    case 1: return launch_score_ws<LAYOUT, 1>(a, s);
+    case 2: return launch_score_ws<LAYOUT, 2>(a, s);
+    case 4: return launch_score_ws<LAYOUT, 4>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,13 +1,16 @@
 // score_pose.h -- device code that builds one pose from its genotype and scores
-// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one, two or four lanes
-// per pose.
+// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one, two or four
+// wavefronts sharing a block of poses.
 //
-// Mapping: a lane (or LP = 2 or 4 lanes, one in each half or quarter of the
-// wavefront) owns a pose.  All ligand data (atoms, torsions, pairs) is uniform
-// across the wavefront (in the scoring kernel it arrives through scalar loads),
-// so every loop below is a scalar loop.  The pose's atom coordinates live in an LDS column: coordinate
-// c of atom i at my[(3 i + c) * STRIDE], STRIDE = poses sharing one LDS row, so
-// the lanes that read the same atom hit consecutive dwords.
+// Mapping: a block of 64 poses, one per lane, is built and scored by WS = 1, 2
+// or 4 wavefronts together (the "split"): lane l of each of them works on pose
+// l, and wavefront h of the block takes its share of the atoms and of the pair
+// records.  All ligand data (atoms, torsions, pairs) is uniform across a
+// wavefront and arrives through scalar loads, so every loop below is a scalar
+// loop and every pair record is an instruction operand as loaded.  A pose's
+// atom coordinates live in an LDS column shared by its WS lanes: coordinate c
+// of atom i at my[(3 i + c) * 64], so the lanes that read the same atom hit
+// consecutive dwords.
 #pragma once
 #include "dock_internal.h"
 
@@ -186,152 +189,92 @@ __device__ __forceinline__ float pair_term(const FFConst &F, const PairRec &P, f
   return fmaf(P.sv, gs, vdw + elec);
 }
 
-template <int STRIDE>
-__device__ __forceinline__ float &at(float *my, int atom, int c) {
-  return my[(3 * atom + c) * STRIDE];
+__device__ __forceinline__ float &at(float *my, int atom, int c) { return my[(3 * atom + c) * kBlock]; }
+
+// The ligand tables as constant memory: the kernels never write them, and
+// uniform loads through these pointers become scalar loads even in kernels
+// that also store to global memory.  (The host pass of the compiler, which
+// only checks the kernels' syntax, sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <class T>
+using cptr = const T *;
+#endif
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
 }
 
-// Pair term of record P with both atoms' coordinates read from this lane's column.
-template <bool HB, int STRIDE>
-__device__ __forceinline__ float pair_energy(const FFConst &F, const PairRec &P, float *my) {
-  const int i = P.ij & 0xffff, j = P.ij >> 16;
-  const float dx = at<STRIDE>(my, i, 0) - at<STRIDE>(my, j, 0);
-  const float dy = at<STRIDE>(my, i, 1) - at<STRIDE>(my, j, 1);
-  const float dz = at<STRIDE>(my, i, 2) - at<STRIDE>(my, j, 2);
-  return pair_term<HB>(F, P, dx, dy, dz);
-}
-
-// Four pair records (one group), fetched with scalar loads.
-struct PairGroup {
-  PairRec r[4];
-  __device__ __forceinline__ void load(const PairRec *__restrict__ p) {
+// The R records of one pair group that wavefront h of a WS-wavefront block
+// evaluates (records h R .. h R + R - 1 of the group's four, R = 4 / WS):
+// uniform, so they are scalar operands as loaded.
+template <int R>
+struct PairSlice {
+  PairRec r[R];
+  __device__ __forceinline__ void load(cptr<PairRec> p) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = p[u];
+    for (int u = 0; u < R; ++u) r[u] = p[u];
   }
 };
 
-// Record q R + u (u < R = 4 / LP) of four, for lane q of an LP-lane pose: the
-// lane picks its records out of the group's uniform ones.  SCALAR: the records
-// sit in scalar registers, and a vector instruction takes at most one scalar
-// operand, so a select first copies its candidates into vector registers.  With
-// four lanes that makes a three-way chain of selects costly, and the pick is
-// arithmetic instead: the sum of the candidates weighted by 0 or 1 (exact for
-// finite records up to the sign of a zero term, which no sum starting at +0
-// carries), and a masked or for the packed atom indices.  With two lanes, and
-// with records in vector registers, selects are cheaper.
-template <int LP, bool SCALAR>
-__device__ __forceinline__ PairRec lane_record(const PairRec r[4], int q, int u) {
-  if constexpr (LP == 1) {
-    return r[u];
-  } else if constexpr (LP == 2) {
-    const PairRec &a = r[u], &b = r[2 + u];
-    PairRec o;
-    o.ij = q ? b.ij : a.ij;
-    o.A = q ? b.A : a.A;
-    o.B = q ? b.B : a.B;
-    o.qq = q ? b.qq : a.qq;
-    o.sv = q ? b.sv : a.sv;
-    return o;
-  } else if constexpr (!SCALAR) {
-    PairRec o = r[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      o.ij = q == k ? r[k].ij : o.ij;
-      o.A = q == k ? r[k].A : o.A;
-      o.B = q == k ? r[k].B : o.B;
-      o.qq = q == k ? r[k].qq : o.qq;
-      o.sv = q == k ? r[k].sv : o.sv;
-    }
-    return o;
-  } else {
-    float w[4];
-    int32_t m[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      w[k] = q == k ? 1.f : 0.f;
-      m[k] = q == k ? -1 : 0;
-    }
-    PairRec o;
-    o.ij = (r[0].ij & m[0]) | (r[1].ij & m[1]) | (r[2].ij & m[2]) | (r[3].ij & m[3]);
-    o.A = r[0].A * w[0];
-    o.B = r[0].B * w[0];
-    o.qq = r[0].qq * w[0];
-    o.sv = r[0].sv * w[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      o.A = fmaf(r[k].A, w[k], o.A);
-      o.B = fmaf(r[k].B, w[k], o.B);
-      o.qq = fmaf(r[k].qq, w[k], o.qq);
-      o.sv = fmaf(r[k].sv, w[k], o.sv);
-    }
-    return o;
-  }
-}
-
-// The R = 4 / LP pairs of a group that lane q of an LP-lane pose evaluates
-// (records q R .. q R + R - 1), with their atoms' coordinates.
-template <int STRIDE, int LP, bool SCALAR>
-struct LaneGroupCoords {
-  static constexpr int R = 4 / LP;
+// The atoms' coordinates of the R pairs of a slice, read from this lane's column.
+template <int R>
+struct SliceCoords {
   float xi[R], yi[R], zi[R], xj[R], yj[R], zj[R];
-  PairRec r[R];
-  __device__ __forceinline__ void load(const PairGroup &G, float *my, int q) {
+  __device__ __forceinline__ void load(const PairSlice<R> &S, float *my) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      r[u] = lane_record<LP, SCALAR>(G.r, q, u);
-      const int i = r[u].ij & 0xffff, j = r[u].ij >> 16;
-      xi[u] = at<STRIDE>(my, i, 0); yi[u] = at<STRIDE>(my, i, 1); zi[u] = at<STRIDE>(my, i, 2);
-      xj[u] = at<STRIDE>(my, j, 0); yj[u] = at<STRIDE>(my, j, 1); zj[u] = at<STRIDE>(my, j, 2);
+      const int i = S.r[u].ij & 0xffff, j = S.r[u].ij >> 16;
+      xi[u] = at(my, i, 0); yi[u] = at(my, i, 1); zi[u] = at(my, i, 2);
+      xj[u] = at(my, j, 0); yj[u] = at(my, j, 1); zj[u] = at(my, j, 2);
     }
-  }
-  __device__ __forceinline__ void energy(const FFConst &F, float e[R]) const {
-#pragma unroll
-    for (int u = 0; u < R; ++u) e[u] = pair_term<false>(F, r[u], xi[u] - xj[u], yi[u] - yj[u], zi[u] - zj[u]);
   }
 };
 
-// Orders LDS writes of one lane before reads by other lanes of the wavefront.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Barrier of the wavefronts that share pose blocks (the workgroup), ordering
+// their LDS writes before the reads that follow.
+template <int WS>
+__device__ __forceinline__ void block_sync() {
+  if constexpr (WS > 1) __syncthreads();
 }
 
-// Energy of the pose whose gene j is g[j * gs] for ligand header H (uniform).
-// LP (1, 2 or 4) lanes build and score one pose together: lane h of the pose
-// is lane p + 64 h / LP of the wavefront.  The lanes share the pose's LDS
-// column (exchanging coordinates through LDS, ordered by wave_sync()) and split
-// its atoms, pair records and 12-10 pairs.  In every form the energy is
-//   (p0 + p1) + (p2 + p3),   p_u = inter over atoms i with i % 4 == u
-//                                + record u of every pair group
-//                                + 12-10 pairs p with p % 4 == u,
-// each p_u summed in index order (inter first, then the groups, then the 12-10
-// pairs); lane h owns p_u for u in [h 4/LP, (h + 1) 4/LP).  So every LP gives
-// the same bits.  Non-finite genes give NaN.  AHEAD: how many pair slices ahead
-// of its use an atom's map loads are issued (more loads in flight, more
-// registers); it does not change the result.  SCALAR: the kernel reads the
-// ligand tables with scalar loads (it stores nothing the compiler cannot tell
-// apart from them), which selects how lanes pick their pair records; it does
-// not change the result either.
-template <int STRIDE, int LAYOUT, int LP = 1, int AHEAD = 1, bool SCALAR = true>
+// Energy of the pose whose gene j is g[j * gs] for ligand header H (uniform),
+// computed by the WS wavefronts of a block together; this is wavefront h.  my
+// is this lane's LDS column, red this lane's slot of the block's reduction area
+// (WS floats at red[w * kBlock], w < WS; unused for WS = 1).  Every wavefront
+// of the workgroup calls this the same number of times with the same ligand
+// (each call holds n_tors + 3 workgroup barriers for WS > 1); lanes with no
+// pose of that ligand compute a value that the caller discards.
+//
+// Wavefront h owns the partial sums p_u for u in [h R, (h + 1) R), R = 4 / WS:
+//   p_u = inter over atoms i with i % 4 == u + record u of every pair group
+//         + 12-10 pairs p with p % 4 == u,
+// each summed in index order (inter first, then the groups, then the 12-10
+// pairs), and the energy is (p0 + p1) + (p2 + p3) for every WS, so the split
+// never changes a bit of the result.  Every wavefront returns the energy.
+// Non-finite genes give NaN.  AHEAD: how many pair slices ahead of its use an
+// atom's map loads are issued (more loads in flight, more registers); it does
+// not change the result.
+template <int LAYOUT, int WS, int AHEAD>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
-                            const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my) {
-  static_assert(LP == 1 || LP == 2 || LP == 4, "one, two or four lanes per pose");
-  constexpr int R = 4 / LP;   // partial sums (and records of a group) per lane
+                            const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my,
+                            float *__restrict__ red, int h) {
+  static_assert(WS == 1 || WS == 2 || WS == 4, "one, two or four wavefronts per block");
+  constexpr int R = 4 / WS;   // partial sums (and records of a group) per wavefront
   const int n = H.n_atoms;
-  const float4 *__restrict__ atoms = L.atoms + H.atom_off;
-  const int32_t *__restrict__ types = L.atom_type + H.atom_off;
-  const int h = LP > 1 ? (int)((threadIdx.x & 63) / (64 / LP)) : 0;
-  if (LP > 1) wave_sync();  // the column's previous pose has been read by all its lanes
+  const cptr<float4> atoms = as_const(L.atoms) + H.atom_off;
+  const cptr<int32_t> types = as_const(L.atom_type) + H.atom_off;
 
   // reference conformation (centred) into the pose's LDS column
-  for (int i = h; i < n; i += LP) {
+  for (int i = h; i < n; i += WS) {
     const float4 a = atoms[i];
-    at<STRIDE>(my, i, 0) = a.x;
-    at<STRIDE>(my, i, 1) = a.y;
-    at<STRIDE>(my, i, 2) = a.z;
+    at(my, i, 0) = a.x;
+    at(my, i, 1) = a.y;
+    at(my, i, 2) = a.z;
   }
-  if (LP > 1) wave_sync();
+  block_sync<WS>();
 
   bool bad = false;
   // the genes are requested before they are needed: the rigid ones here, each
@@ -341,15 +284,15 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   // Algorithm 1, rotatable bonds: rotate each fragment about its current bond
   // axis.  Rotations about current axes commute on a tree, so the torsion order
   // of the genotype is used as is.
-  const TorRec *__restrict__ tors = L.tors + H.tor_off;
+  const cptr<TorRec> tors = as_const(L.tors) + H.tor_off;
   float th_next = H.n_tors > 0 ? g[(7 + tors[0].gene) * gs] : 0.f;
   for (int k = 0; k < H.n_tors; ++k) {
     const TorRec T = tors[k];
     const float th = th_next;
     if (k + 1 < H.n_tors) th_next = g[(7 + tors[k + 1].gene) * gs];
     bad |= !__builtin_isfinite(th);
-    const float ax = at<STRIDE>(my, T.a, 0), ay = at<STRIDE>(my, T.a, 1), az = at<STRIDE>(my, T.a, 2);
-    float ux = at<STRIDE>(my, T.lo, 0) - ax, uy = at<STRIDE>(my, T.lo, 1) - ay, uz = at<STRIDE>(my, T.lo, 2) - az;
+    const float ax = at(my, T.a, 0), ay = at(my, T.a, 1), az = at(my, T.a, 2);
+    float ux = at(my, T.lo, 0) - ax, uy = at(my, T.lo, 1) - ay, uz = at(my, T.lo, 2) - az;
     const float il = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
     ux *= il; uy *= il; uz *= il;
     float s, c;
@@ -358,13 +301,13 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
     const float r00 = fmaf(ux * ux, oc, c), r01 = fmaf(ux * uy, oc, -uz * s), r02 = fmaf(ux * uz, oc, uy * s);
     const float r10 = fmaf(uy * ux, oc, uz * s), r11 = fmaf(uy * uy, oc, c), r12 = fmaf(uy * uz, oc, -ux * s);
     const float r20 = fmaf(uz * ux, oc, -uy * s), r21 = fmaf(uz * uy, oc, ux * s), r22 = fmaf(uz * uz, oc, c);
-    for (int i = T.lo + 1 + h; i < T.hi; i += LP) {
-      const float vx = at<STRIDE>(my, i, 0) - ax, vy = at<STRIDE>(my, i, 1) - ay, vz = at<STRIDE>(my, i, 2) - az;
-      at<STRIDE>(my, i, 0) = ax + fmaf(r00, vx, fmaf(r01, vy, r02 * vz));
-      at<STRIDE>(my, i, 1) = ay + fmaf(r10, vx, fmaf(r11, vy, r12 * vz));
-      at<STRIDE>(my, i, 2) = az + fmaf(r20, vx, fmaf(r21, vy, r22 * vz));
+    for (int i = T.lo + 1 + h; i < T.hi; i += WS) {
+      const float vx = at(my, i, 0) - ax, vy = at(my, i, 1) - ay, vz = at(my, i, 2) - az;
+      at(my, i, 0) = ax + fmaf(r00, vx, fmaf(r01, vy, r02 * vz));
+      at(my, i, 1) = ay + fmaf(r10, vx, fmaf(r11, vy, r12 * vz));
+      at(my, i, 2) = az + fmaf(r20, vx, fmaf(r21, vy, r22 * vz));
     }
-    if (LP > 1) wave_sync();
+    block_sync<WS>();
   }
 
   // Algorithm 1, rigid part: rotate about the ligand origin, then translate
@@ -381,59 +324,58 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   const float R10 = 2.f * (qx * qy + qw * qz), R11 = 1.f - 2.f * (qx * qx + qz * qz), R12 = 2.f * (qy * qz - qw * qx);
   const float R20 = 2.f * (qx * qz - qw * qy), R21 = 2.f * (qy * qz + qw * qx), R22 = 1.f - 2.f * (qx * qx + qy * qy);
 
-  for (int i = h; i < n; i += LP) {
-    const float px = at<STRIDE>(my, i, 0), py = at<STRIDE>(my, i, 1), pz = at<STRIDE>(my, i, 2);
-    at<STRIDE>(my, i, 0) = fmaf(R00, px, fmaf(R01, py, fmaf(R02, pz, tx)));
-    at<STRIDE>(my, i, 1) = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
-    at<STRIDE>(my, i, 2) = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
+  for (int i = h; i < n; i += WS) {
+    const float px = at(my, i, 0), py = at(my, i, 1), pz = at(my, i, 2);
+    at(my, i, 0) = fmaf(R00, px, fmaf(R01, py, fmaf(R02, pz, tx)));
+    at(my, i, 1) = fmaf(R10, px, fmaf(R11, py, fmaf(R12, pz, ty)));
+    at(my, i, 2) = fmaf(R20, px, fmaf(R21, py, fmaf(R22, pz, tz)));
   }
-  if (LP > 1) wave_sync();
+  block_sync<WS>();
 
   // Algorithm 2: the inter-energy loop over atoms and the intra-energy loop over
-  // pairs, interleaved.  Iteration k issues the map loads of the lane's atom of
-  // slot k+1, then evaluates the k-th of equal slices of the pair groups, then
-  // interpolates the atom of slot k from the loads issued one iteration earlier,
-  // so the pair arithmetic covers the latency of the gathers.  Within the pair
-  // loop, the coordinates of group g+1 and the records of group g+2 are
-  // requested before group g is evaluated (the list ends with spare zero
-  // groups to read past).
-  const PairRec *__restrict__ pairs = L.pairs + H.pair_off;
+  // pairs, interleaved.  Iteration k issues the map loads of the wavefront's
+  // atom of slot k + AHEAD, then evaluates the k-th of equal slices of the pair
+  // groups, then interpolates the atom of slot k from loads issued AHEAD
+  // iterations earlier, so the pair arithmetic covers the latency of the
+  // gathers.  Within the pair loop, the coordinates of group g+1 and the records
+  // of group g+2 are requested before group g is evaluated (the list ends with
+  // spare zero groups to read past).
+  const cptr<PairRec> pairs = as_const(L.pairs) + H.pair_off + h * R;
   const int ng = H.n_groups;
-  // The lane's atoms in index order: slot k is atom 4 (k / R) + h R + k % R, of
-  // class h R + k % R; lane 0 has the most slots, the others skip their last.
+  // The wavefront's atoms in index order: slot k is atom 4 (k / R) + h R + k % R,
+  // of class h R + k % R; wavefront 0 has the most slots, the others skip their
+  // last.
   const int slots = R * (n / 4) + min(n % 4, R);
   auto atom_of = [&](int slot) { return 4 * (slot / R) + h * R + slot % R; };
   float inter[R], intra[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) inter[u] = intra[u] = 0.f;
-  // ring[d] holds the loads of the atom of slot k + d; fetched AHEAD slices early
+  // ring[d] holds the loads of the atom of slot k + d
   Corners<LAYOUT> ring[AHEAD + 1];
   auto gather = [&](int slot) {
     const int i = min(atom_of(slot), n - 1);
-    return gather_corners<LAYOUT>(G, maps, types[i], atoms[i].w, at<STRIDE>(my, i, 0), at<STRIDE>(my, i, 1),
-                                  at<STRIDE>(my, i, 2));
+    return gather_corners<LAYOUT>(G, maps, types[i], atoms[i].w, at(my, i, 0), at(my, i, 1), at(my, i, 2));
   };
 #pragma unroll
   for (int d = 0; d < AHEAD; ++d)
     if (d < slots) ring[d] = gather(d);
-  PairGroup A, B;
+  PairSlice<R> A, B;
   A.load(pairs);
   B.load(pairs + 4);
-  LaneGroupCoords<STRIDE, LP, SCALAR> X;
-  X.load(A, my, h);
+  SliceCoords<R> X;
+  X.load(A, my);
   for (int k = 0; k < slots; ++k) {
     const int ka = k + AHEAD;
     if (ka < slots) ring[AHEAD] = gather(ka);
     const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
     for (int gi = g0; gi < g1; ++gi) {
-      LaneGroupCoords<STRIDE, LP, SCALAR> Xn;
-      Xn.load(B, my, h);
-      PairGroup C;
+      SliceCoords<R> Xn;
+      Xn.load(B, my);
+      PairSlice<R> C;
       C.load(pairs + 4 * (gi + 2));
-      float e[R];
-      X.energy(F, e);
 #pragma unroll
-      for (int u = 0; u < R; ++u) intra[u] += e[u];
+      for (int u = 0; u < R; ++u)
+        intra[u] += pair_term<false>(F, A.r[u], X.xi[u] - X.xj[u], X.yi[u] - X.yj[u], X.zi[u] - X.zj[u]);
       A = B;
       B = C;
       X = Xn;
@@ -448,27 +390,35 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
     for (int d = 0; d < AHEAD; ++d) ring[d] = ring[d + 1];
   }
   // 12-10 pairs, four at a time (past the end: all-zero records, which add +0)
-  const PairRec *__restrict__ hb = L.pairs + H.hb_off;
-  const PairRec zero{0, 0.f, 0.f, 0.f, 0.f};
+  const cptr<PairRec> hb = as_const(L.pairs) + H.hb_off;
   for (int p = 0; p < H.n_pairs_hb; p += 4) {
-    PairRec blk[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) blk[u] = p + u < H.n_pairs_hb ? hb[p + u] : zero;
-#pragma unroll
-    for (int u = 0; u < R; ++u) intra[u] += pair_energy<true, STRIDE>(F, lane_record<LP, SCALAR>(blk, h, u), my);
+    for (int u = 0; u < R; ++u) {
+      const int q = p + h * R + u;
+      PairRec P{0, 0.f, 0.f, 0.f, 0.f};
+      if (q < H.n_pairs_hb) P = hb[q];
+      const int i = P.ij & 0xffff, j = P.ij >> 16;
+      intra[u] += pair_term<true>(F, P, at(my, i, 0) - at(my, j, 0), at(my, i, 1) - at(my, j, 1),
+                                  at(my, i, 2) - at(my, j, 2));
+    }
   }
   float part[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) part[u] = inter[u] + intra[u];
   float e;
-  if constexpr (LP == 1) {
+  if constexpr (WS == 1) {
     e = (part[0] + part[1]) + (part[2] + part[3]);
-  } else if constexpr (LP == 2) {
-    const float t = part[0] + part[1];
-    e = t + __shfl_xor(t, 32);
   } else {
-    const float t = part[0] + __shfl_xor(part[0], 16);
-    e = t + __shfl_xor(t, 32);
+    // wavefront h's share, p_{2h} + p_{2h+1} (two wavefronts) or p_h (four),
+    // through LDS to every wavefront of the block, each adding them in the
+    // same order
+    red[h * kBlock] = WS == 2 ? part[0] + part[R - 1] : part[0];
+    block_sync<WS>();
+    if constexpr (WS == 2) {
+      e = red[0] + red[kBlock];
+    } else {
+      e = (red[0] + red[kBlock]) + (red[2 * kBlock] + red[3 * kBlock]);
+    }
   }
   return bad ? __builtin_nanf("") : e;
 }

@@ -42,14 +42,22 @@ struct SearchLaunch {
   const float *proposals;  // [n_ligs][pop][g_stride] or null: scored and taken greedily before the generations
 };
 
-constexpr int kSearchMaxThreads = 256;      // wavefronts per search workgroup: up to 4
+constexpr int kSearchMaxThreads = 768;      // wavefronts per search workgroup: up to 12
 constexpr size_t kLdsPerCU = 160 * 1024;    // gfx950 LDS per compute unit
 
-// Launch shape of a bucket: 1 or 2 lanes per pose, wavefronts per workgroup
-// (0: chosen from the ligand count and the residency the LDS allows).
+// LDS floats of one pose block of the search kernel: the coordinate columns of
+// 64 poses of up to lds_atoms atoms, then (ws > 1) ws rows for the energy
+// reduction.
+__host__ __device__ constexpr size_t search_block_floats(int32_t lds_atoms, int32_t ws) {
+  return ((size_t)lds_atoms * 3 + (ws > 1 ? ws : 0)) * kWave;
+}
+
+// Launch shape of a bucket: the split (1, 2 or 4 wavefronts per block of 64
+// poses) and the blocks per workgroup (0: chosen from the ligand count and the
+// residency the LDS allows).
 struct SearchShape {
-  int32_t lanes_per_pose;
-  int32_t waves;
+  int32_t split;
+  int32_t blocks;
 };
 
 hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, SearchShape shape, hipStream_t s,

@@ -126,18 +126,18 @@ __device__ void trial_individual(const DEParams &p, int n_tor, int lig, int gen,
   }
 }
 
-// Copies genes j = h, h + LP, ... (< G) of a gene-major individual from src to
+// Copies genes j = h, h + WS, ... (< G) of a gene-major individual from src to
 // dst (element j at [j * P]), in blocks whose loads are issued before the stores.
-template <int LP>
+template <int WS>
 __device__ __forceinline__ void copy_genes(const float *__restrict__ src, float *__restrict__ dst, int h, int G,
                                            int P) {
-  for (int j0 = h; j0 < G; j0 += kGeneBlock * LP) {
+  for (int j0 = h; j0 < G; j0 += kGeneBlock * WS) {
     float v[kGeneBlock];
 #pragma unroll
-    for (int k = 0; k < kGeneBlock; ++k) v[k] = src[min(j0 + k * LP, G - 1) * P];
+    for (int k = 0; k < kGeneBlock; ++k) v[k] = src[min(j0 + k * WS, G - 1) * P];
 #pragma unroll
     for (int k = 0; k < kGeneBlock; ++k)
-      if (j0 + k * LP < G) dst[(j0 + k * LP) * P] = v[k];
+      if (j0 + k * WS < G) dst[(j0 + k * WS) * P] = v[k];
   }
 }
 
@@ -157,23 +157,25 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
   trial_individual(p, L.hdr[lig].n_tors, lig, gen, i, g_stride, base, g_stride, 1, trials + t * g_stride, 1);
 }
 
-// The whole search of one ligand, run by one workgroup.  The per-individual
-// steps without a pose (initial genotypes, DE trials, copies) use lane t for
-// individuals t, t + blockDim.x, ...; the scoring passes use LP lanes per
-// individual, lane p + 64 h / LP of a wavefront being lane h of its p-th
-// individual.  The population is worked on in a gene-major copy W (gene j of
+// The whole search of one ligand, run by one workgroup of B blocks of WS
+// wavefronts.  The per-individual steps without a pose (initial genotypes, DE
+// trials, copies) use lane t of the workgroup for individuals t, t + NT, ...;
+// a scoring pass gives lane l of block b the individual c + 64 b + l, built and
+// scored by the block's WS wavefronts together.  Every wavefront of the
+// workgroup takes part in every pass (so all of them meet the same barriers);
+// lanes without an individual score individual 0, in bounds, and drop the
+// result.  The population is worked on in a gene-major copy W (gene j of
 // individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
-// touch neighbouring words; the caller's individual-major population is read
-// at the start and written back at the end.
-template <int LAYOUT, int LP>
-__device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
-  constexpr int kStride = kWave / LP;   // individuals per wavefront in a scoring pass
+// touch neighbouring words; the caller's individual-major population is read at
+// the start and written back at the end.
+template <int LAYOUT, int WS>
+__device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *red) {
   const int t = threadIdx.x, NT = blockDim.x;
-  const int lane = t & (kWave - 1), wave = t / kWave;
-  const int h = lane / kStride;                     // which lane of the individual
-  const int sidx = wave * kStride + (lane & (kStride - 1));
-  const int SNT = NT / LP;
-  const LigHeader H = S.L.hdr[lig];
+  const int wave = __builtin_amdgcn_readfirstlane(t / kWave), lane = t % kWave;
+  const int h = wave % WS;                          // wavefront within its block
+  const int PB = NT / WS;                           // individuals per scoring pass
+  const int slot = (wave / WS) * kBlock + lane;     // this lane's individual in a pass
+  const LigHeader H = as_const(S.L.hdr)[lig];
   const int P = S.p.pop, G = S.g_stride;
   float *pop = S.population + (int64_t)lig * P * G;
   float *E = S.pop_energy + (int64_t)lig * P;
@@ -182,9 +184,7 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   const bool track = S.target != nullptr && S.gen_reached != nullptr;
   const float tgt = track ? S.target[lig] : 0.f;
   auto score = [&](const float *g, int gs) {
-    // the kernel stores to global memory, so the ligand tables arrive in vector
-    // registers (SCALAR = false)
-    return score_pose<kStride, LAYOUT, LP, 1, false>(S.L, S.geom, S.ff, S.maps, H, g, gs, my);
+    return score_pose<LAYOUT, WS, 1>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
   };
   for (int c = 0; c < P; c += NT) {
     const int i = c + t;
@@ -198,12 +198,10 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   }
   __syncthreads();
   if (S.init) {
-    for (int c = 0; c < P; c += SNT) {
-      const int i = c + sidx;
-      if (i < P) {
-        const float e = score(W + i, P);
-        E[i] = e;  // (both lanes of an individual store the same value)
-      }
+    for (int c = 0; c < P; c += PB) {
+      const int i = c + slot;
+      const float e = score(W + (i < P ? i : 0), P);
+      if (i < P && h == 0) E[i] = e;
     }
   }
   // a round of outside proposals (individual-major, one per individual): exact
@@ -211,19 +209,18 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   // at its target
   if (S.proposals && !(S.stop && !S.init && S.gen_reached && S.gen_reached[lig] >= 0)) {
     const float *Q = S.proposals + (int64_t)lig * P * G;
-    for (int c = 0; c < P; c += SNT) {
-      const int i = c + sidx;
-      if (i < P) {
-        const float *pr = Q + (int64_t)i * G;
-        const float e = score(pr, 1);
-        if (e <= E[i]) {
-          for (int j = h; j < G; j += LP) W[j * P + i] = pr[j];
-          E[i] = e;  // (both lanes of an individual store the same value)
-        }
+    for (int c = 0; c < P; c += PB) {
+      const int i = c + slot;
+      const float *pr = Q + (int64_t)(i < P ? i : 0) * G;
+      const float e = score(pr, 1);
+      // every wavefront of the block takes the same decision (wavefront 0
+      // stores E[i] = e only when e <= E[i], so a late read sees e itself)
+      if (i < P && e <= E[i]) {
+        for (int j = h; j < G; j += WS) W[j * P + i] = pr[j];
+        if (h == 0) E[i] = e;
       }
     }
   }
-  // the energies just written come from the scoring lanes of each individual
   __syncthreads();
   int reached = -1;
   if (track) {
@@ -240,30 +237,30 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
   // with S.stop, the search of a ligand ends once its best has reached the target
   const bool stop = track && S.stop;
   const int g_end = (stop && reached >= 0) ? S.p.first_gen : S.p.first_gen + S.p.n_gen;
-  for (int g = S.p.first_gen; g < g_end; ++g) {
+  for (int gen = S.p.first_gen; gen < g_end; ++gen) {
     // every trial of the generation is drawn from the population as it stood
     for (int c = 0; c < P; c += NT) {
       const int i = c + t;
-      if (i < P) trial_individual(S.p, H.n_tors, lig, g, i, G, W, 1, P, T + i, P);
+      if (i < P) trial_individual(S.p, H.n_tors, lig, gen, i, G, W, 1, P, T + i, P);
     }
     __syncthreads();
     int hit = 0;
-    for (int c = 0; c < P; c += SNT) {
-      const int i = c + sidx;
+    for (int c = 0; c < P; c += PB) {
+      const int i = c + slot;
+      const float e = score(T + (i < P ? i : 0), P);
       if (i < P) {
-        const float e = score(T + i, P);
         float ei = E[i];
         if (e <= ei) {
-          copy_genes<LP>(T + i, W + i, h, G, P);
+          copy_genes<WS>(T + i, W + i, h, G, P);
           ei = e;
-          E[i] = e;  // (both lanes of an individual store the same value)
+          if (h == 0) E[i] = e;
         }
         hit |= ei <= tgt;
       }
     }
     if (track) {
       hit = __syncthreads_or(hit);
-      if (reached < 0 && hit) reached = g + 1;
+      if (reached < 0 && hit) reached = gen + 1;
       if (stop && reached >= 0) break;
     } else {
       __syncthreads();
@@ -294,26 +291,24 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my) {
 }
 
 // Persistent: each workgroup keeps taking ligands from the queue until none is
-// left.  Wavefront w of the group keeps its poses' coordinates in its own LDS
-// region of lds_atoms * 3 rows of 64 / LP dwords.  With the line layouts the
-// register budget is that of three wavefronts per SIMD (168 VGPRs, against
-// 172-217 unbounded): what does not fit is reloaded once per ligand, generation
-// or scoring pass, never inside a pose.  The other layouts keep two.
-template <int LAYOUT, int LP>
-__global__ __launch_bounds__(kSearchMaxThreads, (LAYOUT == kQuadLine || LAYOUT == kPairLine) ? 3 : 2) void
-search_kernel(SearchLaunch S) {
-  constexpr int kStride = kWave / LP;
+// left.  Block b of the workgroup keeps its poses' coordinates in its own LDS
+// region of lds_atoms * 3 rows of 64 dwords, followed (WS > 1) by WS rows for
+// the energy reduction.
+template <int LAYOUT, int WS>
+__global__ __launch_bounds__(kSearchMaxThreads) void search_kernel(SearchLaunch S) {
   extern __shared__ float lds[];
   __shared__ int s_q;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  float *my = lds + (size_t)wave * 3 * S.lds_atoms * kStride + (lane & (kStride - 1));
+  const int block = __builtin_amdgcn_readfirstlane((threadIdx.x / kWave) / WS), lane = threadIdx.x % kWave;
+  float *base = lds + (size_t)block * search_block_floats(S.lds_atoms, WS);
+  float *my = base + lane;
+  float *red = base + 3 * S.lds_atoms * kBlock + lane;
   for (;;) {
     if (threadIdx.x == 0) s_q = atomicAdd(S.queue, 1);
     __syncthreads();
     const int q = s_q;
     __syncthreads();
     if (q >= S.n_order) break;
-    search_ligand<LAYOUT, LP>(S, S.order[q], my);
+    search_ligand<LAYOUT, WS>(S, S.order[q], my, red);
   }
 }
 
@@ -342,18 +337,17 @@ hipError_t launch_fill_i32(int32_t *p, int32_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int LAYOUT, int LP>
-static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t waves, hipStream_t s,
+template <int LAYOUT, int WS>
+static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t blocks, hipStream_t s,
                                   const char **step) {
-  // Wavefronts per workgroup, w: up to one per 64 / LP individuals.  Each
-  // wavefront's LDS region is sized for the bucket's largest ligand, so a larger
-  // w can leave fewer wavefronts resident per CU.  Unless the caller fixes w,
-  // pick the w that minimises (rounds of resident ligands) x (scoring passes per
-  // generation).
-  auto kernel = (const void *)search_kernel<LAYOUT, LP>;
-  const int per_pass = kWave / LP;
-  const size_t per_wave = (size_t)S.lds_atoms * 3 * per_pass * sizeof(float);
-  const int want = std::min((S.p.pop + per_pass - 1) / per_pass, kSearchMaxThreads / kWave);
+  // Blocks per workgroup, b: up to one per 64 individuals.  Each block's LDS is
+  // sized for the bucket's largest ligand, so a larger b can leave fewer
+  // wavefronts resident per CU.  Unless the caller fixes b, pick the b that
+  // minimises (rounds of resident ligands) x (scoring passes per generation).
+  auto kernel = (const void *)search_kernel<LAYOUT, WS>;
+  const size_t per_block = search_block_floats(S.lds_atoms, WS) * sizeof(float);
+  const int max_b = kSearchMaxThreads / (kWave * WS);
+  const int want = std::min((S.p.pop + kBlock - 1) / kBlock, max_b);
   // The dynamic LDS allowance is what the CU holds less the kernel's static LDS
   // (its __shared__ variables plus what the compiler adds for block reductions).
   hipFuncAttributes fa;
@@ -361,11 +355,11 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t w
   if (hipError_t e = hipFuncGetAttributes(&fa, kernel); e != hipSuccess) return e;
   if (fa.sharedSizeBytes >= kLdsPerCU) return hipErrorInvalidConfiguration;
   const size_t max_dyn = kLdsPerCU - fa.sharedSizeBytes;
-  const int max_w = std::max(want, std::min(waves, kSearchMaxThreads / kWave));
+  const int top_b = std::max(want, std::min(blocks, max_b));
   *step = "hipFuncSetAttribute (largest size)";
-  if (per_wave * max_w > 65536) {
+  if (per_block * top_b > 65536) {
     hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)std::min<size_t>(max_dyn, per_wave * max_w));
+                                       (int)std::min<size_t>(max_dyn, per_block * top_b));
     if (e != hipSuccess) return e;
   }
   // Resident workgroups per CU: bounded by the CU's LDS (dynamic + static per
@@ -375,66 +369,67 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t w
   // waits for a free slot, which a persistent kernel with a work queue tolerates.
   const int vgprs = std::max(8, (fa.numRegs + 7) / 8 * 8);
   const int waves_per_cu = 4 * std::min(8, 512 / vgprs);
-  auto resident = [&](int w, int *blocks) -> hipError_t {
-    *blocks = 0;
-    if (per_wave * w > max_dyn) return hipSuccess;
+  auto resident = [&](int b, int *groups) -> hipError_t {
+    *groups = 0;
+    if (per_block * b > max_dyn) return hipSuccess;
     *step = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, kernel, w * kWave, per_wave * w);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, kernel, b * WS * kWave, per_block * b);
     if (e != hipSuccess) return e;
-    const int by_lds = (int)(kLdsPerCU / (per_wave * w + fa.sharedSizeBytes));
-    *blocks = std::max(*blocks, std::min(by_lds, waves_per_cu / w));
+    const int by_lds = (int)(kLdsPerCU / (per_block * b + fa.sharedSizeBytes));
+    *groups = std::max(*groups, std::min(by_lds, waves_per_cu / (b * WS)));
     return hipSuccess;
   };
-  int best_w = 0, best_blocks = 0;
-  if (waves > 0) {
+  int best_b = 0, best_groups = 0;
+  if (blocks > 0) {
     // the caller's count, lowered to what the LDS of one CU holds
-    for (best_w = std::min(waves, kSearchMaxThreads / kWave); best_w > 1 && per_wave * best_w > max_dyn; --best_w) {
+    for (best_b = std::min(blocks, max_b); best_b > 1 && per_block * best_b > max_dyn; --best_b) {
     }
-    if (hipError_t e = resident(best_w, &best_blocks); e != hipSuccess) return e;
-    if (best_blocks < 1) return hipErrorInvalidConfiguration;
+    if (hipError_t e = resident(best_b, &best_groups); e != hipSuccess) return e;
+    if (best_groups < 1) return hipErrorInvalidConfiguration;
   } else {
     int64_t best_cost = -1;
-    for (int w = 1; w <= want; ++w) {
-      int blocks = 0;
-      if (hipError_t e = resident(w, &blocks); e != hipSuccess) return e;
-      if (blocks < 1) continue;
-      const int64_t slots = (int64_t)n_cu * blocks;
+    for (int b = 1; b <= want; ++b) {
+      int groups = 0;
+      if (hipError_t e = resident(b, &groups); e != hipSuccess) return e;
+      if (groups < 1) continue;
+      const int64_t slots = (int64_t)n_cu * groups;
       const int64_t rounds = (S.n_order + slots - 1) / slots;
-      const int64_t passes = (S.p.pop + w * per_pass - 1) / (w * per_pass);
-      if (best_cost < 0 || rounds * passes < best_cost) best_cost = rounds * passes, best_w = w, best_blocks = blocks;
+      const int64_t passes = (S.p.pop + b * kBlock - 1) / (b * kBlock);
+      if (best_cost < 0 || rounds * passes < best_cost) best_cost = rounds * passes, best_b = b, best_groups = groups;
     }
-    if (best_w == 0) return hipErrorInvalidConfiguration;
+    if (best_b == 0) return hipErrorInvalidConfiguration;
   }
-  const size_t lds = per_wave * best_w;
-  const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * best_blocks);
+  const size_t lds = per_block * best_b;
+  const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * best_groups);
   *step = "search kernel launch";
-  void (*const fn)(SearchLaunch) = search_kernel<LAYOUT, LP>;
-  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(best_w * kWave), lds, s, S);
+  void (*const fn)(SearchLaunch) = search_kernel<LAYOUT, WS>;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(best_b * WS * kWave), lds, s, S);
   return hipGetLastError();
 }
 
 template <int LAYOUT>
-static hipError_t launch_search_lp(const SearchLaunch &S, int32_t n_cu, SearchShape shape, hipStream_t s,
+static hipError_t launch_search_ws(const SearchLaunch &S, int32_t n_cu, SearchShape shape, hipStream_t s,
                                    const char **step) {
-  if (shape.lanes_per_pose == 4) return launch_search_t<LAYOUT, 4>(S, n_cu, shape.waves, s, step);
-  if (shape.lanes_per_pose == 2) return launch_search_t<LAYOUT, 2>(S, n_cu, shape.waves, s, step);
-  return launch_search_t<LAYOUT, 1>(S, n_cu, shape.waves, s, step);
+  if (shape.split == 4) return launch_search_t<LAYOUT, 4>(S, n_cu, shape.blocks, s, step);
+  if (shape.split == 2) return launch_search_t<LAYOUT, 2>(S, n_cu, shape.blocks, s, step);
+  return launch_search_t<LAYOUT, 1>(S, n_cu, shape.blocks, s, step);
 }
 
 bool search_shape_fits(int32_t lds_atoms, SearchShape shape) {
-  const size_t per_wave = (size_t)lds_atoms * 3 * (kWave / shape.lanes_per_pose) * sizeof(float);
-  return per_wave * (size_t)std::max(shape.waves, 1) + 1024 <= kLdsPerCU;
+  const size_t per_block = search_block_floats(lds_atoms, shape.split) * sizeof(float);
+  return per_block * (size_t)std::max(shape.blocks, 1) + 1024 <= kLdsPerCU &&
+         std::max(shape.blocks, 1) * shape.split * kWave <= kSearchMaxThreads;
 }
 
 hipError_t launch_search(const SearchLaunch &S, int32_t layout, int32_t n_cu, SearchShape shape, hipStream_t s,
                          const char **step) {
   if (S.n_order <= 0) return hipSuccess;
   switch (layout) {
-    case kLinear: return launch_search_lp<kLinear>(S, n_cu, shape, s, step);
-    case kZPair: return launch_search_lp<kZPair>(S, n_cu, shape, s, step);
-    case kYZQuad: return launch_search_lp<kYZQuad>(S, n_cu, shape, s, step);
-    case kQuadLine: return launch_search_lp<kQuadLine>(S, n_cu, shape, s, step);
-    case kPairLine: return launch_search_lp<kPairLine>(S, n_cu, shape, s, step);
+    case kLinear: return launch_search_ws<kLinear>(S, n_cu, shape, s, step);
+    case kZPair: return launch_search_ws<kZPair>(S, n_cu, shape, s, step);
+    case kYZQuad: return launch_search_ws<kYZQuad>(S, n_cu, shape, s, step);
+    case kQuadLine: return launch_search_ws<kQuadLine>(S, n_cu, shape, s, step);
+    case kPairLine: return launch_search_ws<kPairLine>(S, n_cu, shape, s, step);
   }
   return hipErrorInvalidValue;
 }

@@ -77,8 +77,8 @@ _SIGS = {
     "dock_ligand_pair_count": [_P, C.c_int32, _P],
     "dock_destroy_ligands": [_P],
     "dock_score_poses": [_P, _P, _P, _P, C.c_int32, C.c_int64, _P, _P],
-    "dock_score_set_lanes_per_pose": [C.c_int32],
-    "dock_score_lanes_per_pose": [_P, _P],
+    "dock_score_set_split": [C.c_int32],
+    "dock_score_split": [_P, _P],
     "dock_de_init": [_P, _P, C.c_int32, _P, _P],
     "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
@@ -128,18 +128,47 @@ def _stream(stream):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dptr(t, dtype_name: str, what: str):
-    """Device pointer of a contiguous torch tensor of the expected dtype (or None)."""
-    if t is None:
-        return None
+def _bufs(device: int, *specs):
+    """Device pointers (None for None) of the torch tensors in specs, each given
+    as (tensor, dtype name, what, least element count).  Every tensor is checked
+    -- type, dtype and length first, for all of them, then that it lies
+    contiguous on the handle's device -- before any pointer reaches the library,
+    whose kernels write through them."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{what}: expected a device tensor")
-    if str(t.dtype) != f"torch.{dtype_name}":
-        raise TypeError(f"{what}: expected {dtype_name}, got {t.dtype}")
-    if not t.is_contiguous():
-        raise ValueError(f"{what}: tensor must be contiguous")
-    return C.c_void_p(t.data_ptr())
+    for t, dtype_name, what, need in specs:
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{what}: expected a torch tensor")
+        if str(t.dtype) != f"torch.{dtype_name}":
+            raise TypeError(f"{what}: expected {dtype_name}, got {t.dtype}")
+        if t.numel() < need:
+            raise ValueError(f"{what}: {t.numel()} elements, at least {need} needed")
+    out = []
+    for t, _, what, _ in specs:
+        if t is None:
+            out.append(None)
+            continue
+        if not t.is_cuda:
+            raise TypeError(f"{what}: expected a device tensor")
+        if t.device.index != device:
+            raise ValueError(f"{what}: on device {t.device.index}, the handle is on device {device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what}: tensor must be contiguous")
+        out.append(C.c_void_p(t.data_ptr()))
+    return out
+
+
+def _buf(t, dtype_name: str, what: str, need: int, device: int):
+    """_bufs for one tensor."""
+    return _bufs(device, (t, dtype_name, what, need))[0]
+
+
+def _rows(t, what: str) -> int:
+    """Row count of a 2-D (or higher) tensor argument."""
+    if t is None or t.dim() < 2:
+        raise ValueError(f"{what}: expected a tensor of at least two dimensions")
+    return int(t.shape[0])
 
 
 class _Keep:
@@ -216,7 +245,7 @@ def dock_create_pocket(grid, maps, ff, device: int = 0, layout: int = DOCK_LAYOU
     if isinstance(maps, np.ndarray):
         ptr, on_dev = keep.arr(maps, np.float32), 0
     else:
-        ptr, on_dev = _dptr(maps, "float32", "maps"), 1
+        ptr, on_dev = _buf(maps, "float32", "maps", (grid.n_types + 2) * int(np.prod(grid.dims)), device), 1
     _check(_lib.dock_create_pocket(C.byref(G), ptr, on_dev, C.byref(F), layout, device, C.byref(out)))
     return Pocket(out, grid, device)
 
@@ -235,7 +264,10 @@ def dock_create_pocket_from_receptor(grid, ff, receptor, device: int = 0, layout
 
 
 def dock_pocket_maps(pocket: Pocket, maps_out, stream=None):
-    _check(_lib.dock_pocket_maps(pocket.handle, _dptr(maps_out, "float32", "maps_out"), _stream(stream)))
+    g = pocket.grid
+    need = (g.n_types + 2) * int(np.prod(g.dims))
+    _check(_lib.dock_pocket_maps(pocket.handle, _buf(maps_out, "float32", "maps_out", need, pocket.device),
+                                 _stream(stream)))
 
 
 def dock_create_ligands(pocket: Pocket, ligands) -> Ligands:
@@ -253,22 +285,22 @@ def dock_create_ligands(pocket: Pocket, ligands) -> Ligands:
 
 def dock_score_poses(pocket: Pocket, ligs: Ligands, genotypes, energies, pose_ligand=None, stream=None):
     """genotypes: float32 [n, g_stride] device tensor; energies: float32 [n] device tensor."""
-    n = int(genotypes.shape[0])
-    if energies.numel() < n:
-        raise ValueError("energies too small")
-    _check(_lib.dock_score_poses(pocket.handle, ligs.handle, _dptr(pose_ligand, "int32", "pose_ligand"),
-                                 _dptr(genotypes, "float32", "genotypes"), int(genotypes.shape[1]), n,
-                                 _dptr(energies, "float32", "energies"), _stream(stream)))
+    n = _rows(genotypes, "genotypes")
+    gs = int(np.prod(genotypes.shape[1:]))
+    pl, g, e = _bufs(pocket.device, (pose_ligand, "int32", "pose_ligand", n),
+                     (genotypes, "float32", "genotypes", n * gs), (energies, "float32", "energies", n))
+    _check(_lib.dock_score_poses(pocket.handle, ligs.handle, pl, g, gs, n, e, _stream(stream)))
 
 
-def dock_score_set_lanes_per_pose(lanes_per_pose: int):
-    """Lanes per pose of the scoring kernel (1, 2 or 4; 0 = automatic), process-wide."""
-    _check(_lib.dock_score_set_lanes_per_pose(int(lanes_per_pose)))
+def dock_score_set_split(split: int):
+    """Wavefronts per block of 64 poses of the scoring kernel (1, 2 or 4; 0 =
+    automatic), process-wide."""
+    _check(_lib.dock_score_set_split(int(split)))
 
 
-def dock_score_lanes_per_pose(ligs: Ligands) -> int:
+def dock_score_split(ligs: Ligands) -> int:
     out = C.c_int32()
-    _check(_lib.dock_score_lanes_per_pose(ligs.handle, C.byref(out)))
+    _check(_lib.dock_score_split(ligs.handle, C.byref(out)))
     return out.value
 
 
@@ -297,27 +329,44 @@ class SearchParams:
                        self.proposal_every, self.proposal_until)
 
 
+def _pop_sizes(ligs: Ligands, params: SearchParams, population):
+    """(g_stride, elements of a population, of its energies) for a population tensor."""
+    g = int(population.shape[-1])
+    n = ligs.n * max(int(params.pop_size), 0)
+    return g, n * g, n
+
+
 def dock_de_init(ligs: Ligands, params: SearchParams, population, stream=None):
     P = params._c()
-    _check(_lib.dock_de_init(ligs.handle, C.byref(P), int(population.shape[-1]),
-                             _dptr(population, "float32", "population"), _stream(stream)))
+    g, npg, _ = _pop_sizes(ligs, params, population)
+    _check(_lib.dock_de_init(ligs.handle, C.byref(P), g,
+                             _buf(population, "float32", "population", npg, ligs.pocket.device), _stream(stream)))
 
 
 def dock_de_trials(ligs: Ligands, params: SearchParams, generation: int, population, trials, stream=None):
     P = params._c()
-    _check(_lib.dock_de_trials(ligs.handle, C.byref(P), generation, int(population.shape[-1]),
-                               _dptr(population, "float32", "population"), _dptr(trials, "float32", "trials"),
-                               _stream(stream)))
+    g, npg, _ = _pop_sizes(ligs, params, population)
+    pp, tp = _bufs(ligs.pocket.device, (population, "float32", "population", npg), (trials, "float32", "trials", npg))
+    _check(_lib.dock_de_trials(ligs.handle, C.byref(P), generation, g, pp, tp, _stream(stream)))
 
 
 def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy, best_genotypes,
                 best_energies, target=None, gen_reached=None, stream=None):
     P = params._c()
-    _check(_lib.dock_search(pocket.handle, ligs.handle, C.byref(P), int(population.shape[-1]),
-                            _dptr(population, "float32", "population"), _dptr(pop_energy, "float32", "pop_energy"),
-                            _dptr(best_genotypes, "float32", "best_genotypes"),
-                            _dptr(best_energies, "float32", "best_energies"), _dptr(target, "float32", "target"),
-                            _dptr(gen_reached, "int32", "gen_reached"), _stream(stream)))
+    args = _search_buffers(pocket, ligs, params, population, pop_energy, best_genotypes, best_energies, target,
+                           gen_reached)
+    _check(_lib.dock_search(pocket.handle, ligs.handle, C.byref(P), *args, _stream(stream)))
+
+
+def _search_buffers(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy, best_genotypes,
+                    best_energies, target, gen_reached):
+    """g_stride and the checked pointers of a search's buffers."""
+    g, npg, npe = _pop_sizes(ligs, params, population)
+    n = ligs.n
+    return (g, *_bufs(pocket.device, (population, "float32", "population", npg),
+                      (pop_energy, "float32", "pop_energy", npe), (best_genotypes, "float32", "best_genotypes", n * g),
+                      (best_energies, "float32", "best_energies", n), (target, "float32", "target", n),
+                      (gen_reached, "int32", "gen_reached", n)))
 
 
 def dock_gather_probe(pocket: Pocket, ligs: Ligands, lig: int, box_lo, box_hi, out, per_lane: int, seed: int = 1,
@@ -327,13 +376,13 @@ def dock_gather_probe(pocket: Pocket, ligs: Ligands, lig: int, box_lo, box_hi, o
     lo = (C.c_float * 3)(*box_lo)
     hi = (C.c_float * 3)(*box_hi)
     _check(_lib.dock_gather_probe(pocket.handle, ligs.handle, lig, lo, hi, int(out.numel()), per_lane, in_flight,
-                                  seed, _dptr(out, "float32", "out"), _stream(stream)))
+                                  seed, _buf(out, "float32", "out", 0, pocket.device), _stream(stream)))
 
 
 def dock_pair_probe(pocket: Pocket, out, per_lane: int, stream=None):
     """Pair terms alone on register coordinates (roofline probe)."""
-    _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane, _dptr(out, "float32", "out"),
-                                _stream(stream)))
+    _check(_lib.dock_pair_probe(pocket.handle, int(out.numel()), per_lane,
+                                _buf(out, "float32", "out", 0, pocket.device), _stream(stream)))
 
 
 # ---------------------------------------------------------------- search plans
@@ -356,13 +405,9 @@ def dock_search_plan_create(pocket: Pocket, ligs: Ligands, params: SearchParams,
                             best_genotypes, best_energies, target=None, gen_reached=None) -> SearchPlan:
     P = params._c()
     out = C.c_void_p()
-    _check(_lib.dock_search_plan_create(pocket.handle, ligs.handle, C.byref(P), int(population.shape[-1]),
-                                        _dptr(population, "float32", "population"),
-                                        _dptr(pop_energy, "float32", "pop_energy"),
-                                        _dptr(best_genotypes, "float32", "best_genotypes"),
-                                        _dptr(best_energies, "float32", "best_energies"),
-                                        _dptr(target, "float32", "target"),
-                                        _dptr(gen_reached, "int32", "gen_reached"), C.byref(out)))
+    args = _search_buffers(pocket, ligs, params, population, pop_energy, best_genotypes, best_energies, target,
+                           gen_reached)
+    _check(_lib.dock_search_plan_create(pocket.handle, ligs.handle, C.byref(P), *args, C.byref(out)))
     return SearchPlan(out, (pocket, ligs, params.proposal, population, pop_energy, best_genotypes, best_energies,
                             target, gen_reached))
 
@@ -376,14 +421,14 @@ DOCK_SEARCH_BUCKETS = 5
 
 
 class _Shape(C.Structure):
-    _fields_ = [("max_atoms", C.c_int32), ("lanes_per_pose", C.c_int32), ("waves_per_group", C.c_int32)]
+    _fields_ = [("max_atoms", C.c_int32), ("split", C.c_int32), ("blocks_per_group", C.c_int32)]
 
 
 def dock_search_shapes(ligs: Ligands):
-    """[(max_atoms, lanes_per_pose, waves_per_group)] per ligand-size bucket."""
+    """[(max_atoms, split, blocks_per_group)] per ligand-size bucket."""
     arr = (_Shape * DOCK_SEARCH_BUCKETS)()
     _check(_lib.dock_search_shapes(ligs.handle, arr))
-    return [(a.max_atoms, a.lanes_per_pose, a.waves_per_group) for a in arr]
+    return [(a.max_atoms, a.split, a.blocks_per_group) for a in arr]
 
 
 def dock_search_set_shapes(ligs: Ligands, shapes):
@@ -445,52 +490,57 @@ def dock_mlp_get_params(net: Mlp) -> np.ndarray:
 
 def dock_mlp_forward(net: Mlp, x, y, stream=None):
     """x: float32 [n, 96] device tensor; y: float32 [n, 32] device tensor."""
-    n = int(x.shape[0])
-    if y.numel() < n * DOCK_MLP_OUT:
-        raise ValueError("y too small")
-    _check(_lib.dock_mlp_forward(net.handle, _dptr(x, "float32", "x"), n, _dptr(y, "float32", "y"),
-                                 _stream(stream)))
+    n = _rows(x, "x")
+    xp, yp = _bufs(net.device, (x, "float32", "x", n * DOCK_MLP_IN), (y, "float32", "y", n * DOCK_MLP_OUT))
+    _check(_lib.dock_mlp_forward(net.handle, xp, n, yp, _stream(stream)))
 
 
 def dock_mlp_gradients(net: Mlp, x, target, grads, loss, weight=None, stream=None):
-    n = int(x.shape[0])
-    _check(_lib.dock_mlp_gradients(net.handle, _dptr(x, "float32", "x"), _dptr(target, "float32", "target"),
-                                   _dptr(weight, "float32", "weight"), n, _dptr(grads, "float32", "grads"),
-                                   _dptr(loss, "float32", "loss"), _stream(stream)))
+    n = _rows(x, "x")
+    xp, tp, wp, gp, lp = _bufs(net.device, (x, "float32", "x", n * DOCK_MLP_IN),
+                               (target, "float32", "target", n * DOCK_MLP_OUT), (weight, "float32", "weight", n),
+                               (grads, "float32", "grads", DOCK_MLP_PARAMS), (loss, "float32", "loss", 1))
+    _check(_lib.dock_mlp_gradients(net.handle, xp, tp, wp, n, gp, lp, _stream(stream)))
 
 
 def dock_mlp_train(net: Mlp, x, target, batch: int, n_steps: int, lr: float, weight=None, order=None, losses=None,
                    stream=None):
     """Adam steps on minibatches of the data set x [n, 96] / target [n, 32]: the rows
     order[0..] (int32 device tensor of row indices) or all rows in order."""
-    n = int(x.shape[0])
+    n = _rows(x, "x")
     n_rows = n if order is None else int(order.numel())
-    _check(_lib.dock_mlp_train(net.handle, _dptr(x, "float32", "x"), _dptr(target, "float32", "target"),
-                               _dptr(weight, "float32", "weight"), n, _dptr(order, "int32", "order"), n_rows,
-                               batch, n_steps, lr, _dptr(losses, "float32", "losses"), _stream(stream)))
+    xp, tp, wp, op, lp = _bufs(net.device, (x, "float32", "x", n * DOCK_MLP_IN),
+                               (target, "float32", "target", n * DOCK_MLP_OUT), (weight, "float32", "weight", n),
+                               (order, "int32", "order", 0), (losses, "float32", "losses", max(n_steps, 0)))
+    _check(_lib.dock_mlp_train(net.handle, xp, tp, wp, n, op, n_rows, batch, n_steps, lr, lp, _stream(stream)))
 
 
 def dock_ligand_descriptors(ligs: Ligands, out, stream=None):
-    _check(_lib.dock_ligand_descriptors(ligs.handle, _dptr(out, "float32", "out"), _stream(stream)))
+    _check(_lib.dock_ligand_descriptors(ligs.handle, _buf(out, "float32", "out", ligs.n * DOCK_DESC,
+                                                          ligs.pocket.device), _stream(stream)))
 
 
 def dock_mlp_features(ligs: Ligands, params: SearchParams, population, x, stream=None):
     P = params._c()
-    _check(_lib.dock_mlp_features(ligs.handle, C.byref(P), int(population.shape[-1]),
-                                  _dptr(population, "float32", "population"), _dptr(x, "float32", "x"),
-                                  _stream(stream)))
+    g, npg, n = _pop_sizes(ligs, params, population)
+    pp, xp = _bufs(ligs.pocket.device, (population, "float32", "population", npg),
+                   (x, "float32", "x", n * DOCK_MLP_IN))
+    _check(_lib.dock_mlp_features(ligs.handle, C.byref(P), g, pp, xp, _stream(stream)))
 
 
 def dock_mlp_moves(ligs: Ligands, params: SearchParams, from_pop, to_pop, out, stream=None):
     P = params._c()
-    _check(_lib.dock_mlp_moves(ligs.handle, C.byref(P), int(from_pop.shape[-1]),
-                               _dptr(from_pop, "float32", "from"), _dptr(to_pop, "float32", "to"),
-                               _dptr(out, "float32", "out"), _stream(stream)))
+    g, npg, n = _pop_sizes(ligs, params, from_pop)
+    fp, tp, op = _bufs(ligs.pocket.device, (from_pop, "float32", "from", npg), (to_pop, "float32", "to", npg),
+                       (out, "float32", "out", n * DOCK_MLP_OUT))
+    _check(_lib.dock_mlp_moves(ligs.handle, C.byref(P), g, fp, tp, op, _stream(stream)))
 
 
 def dock_propose(ligs: Ligands, net: Mlp, params: SearchParams, generation: int, alpha_max: float, population,
                  proposals, stream=None):
     P = params._c()
-    _check(_lib.dock_propose(ligs.handle, net.handle, C.byref(P), generation, alpha_max,
-                             int(population.shape[-1]), _dptr(population, "float32", "population"),
-                             _dptr(proposals, "float32", "proposals"), _stream(stream)))
+    g, npg, _ = _pop_sizes(ligs, params, population)
+    pp, qp = _bufs(ligs.pocket.device, (population, "float32", "population", npg),
+                   (proposals, "float32", "proposals", npg))
+    _check(_lib.dock_propose(ligs.handle, net.handle, C.byref(P), generation, alpha_max, g, pp, qp,
+                             _stream(stream)))

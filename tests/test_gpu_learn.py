@@ -441,8 +441,11 @@ def test_trained_network_gains(dk):
     """What the trained network adds: trained on plain runs over 1500 training
     ligands, the learned search reaches the plain search's final median best
     (+ 0.1 kcal/mol) over 600 other ligands in less GPU time, and is ahead at
-    generation 100.  (The bench measures the same on the full 10000 / 5000
-    ligand sets.)"""
+    generation 100.  The same proposal rounds from the untrained network (its
+    seeded initial weights) are the control that separates training from the
+    extra exactly scored proposals: the trained network must reach the level
+    in less GPU time than it.  (The bench measures the same on the full 10000 /
+    5000 ligand sets.)"""
     from paper_2509_12232_amd import proposal as pr
     c = synth.CONFIGS[3]
     nt = c["n_types"]
@@ -465,7 +468,15 @@ def test_trained_network_gains(dk):
     assert learned[g100][2] < plain[g100][2] - 1.0, (learned[g100], plain[g100])
     t_plain, _ = pr.time_to_level(plain, level)
     t_learned, _ = pr.time_to_level(learned, level)
+    untrained, _ = pr.anytime(pocket, L_ev, P, stride, dk.dock_mlp_create(0, pr.TrainConfig().seed),
+                              pr.ProposalConfig())
+    t_untrained, _ = pr.time_to_level(untrained, level)
+    print(f"GPU ms to the plain level: plain {t_plain}, untrained rounds {t_untrained}, trained {t_learned}; "
+          f"median at generation 100: plain {plain[g100][2]:.3f}, untrained {untrained[g100][2]:.3f}, "
+          f"trained {learned[g100][2]:.3f}", flush=True)
     assert t_learned is not None and t_learned < t_plain, (t_learned, t_plain)
+    assert t_untrained is None or t_learned < t_untrained, (t_learned, t_untrained)
+    assert learned[g100][2] < untrained[g100][2], (learned[g100], untrained[g100])
 
 
 def test_non_finite_proposals_fall_back_to_plain_de(dk):

@@ -50,7 +50,7 @@ def test_config0_single_ligand_parity(dk, ora, layout):
 def test_pair_line_gives_the_quad_line_bits(dk):
     """The pair-line and quad-line layouts hold the same rounded values (type
     quads, E + D and E - D quads) and the kernel interpolates them in the same
-    order, so energies are the same bits in every lanes-per-pose shape, for atoms
+    order, so energies are the same bits for every scoring split, for atoms
     of both charge signs and for poses reaching past the grid box."""
     ff, rec, grid, maps = system(0)
     lig = synth.make_ligand(1, 0, 24, 6, 8)
@@ -64,11 +64,11 @@ def test_pair_line_gives_the_quad_line_bits(dk):
             pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
             ligs = dk.dock_create_ligands(pocket, [lig])
             for lp in (1, 2, 4):
-                print("case: quad-line vs pair-line bits, layout", layout, "lanes", lp, flush=True)
-                dk.dock_score_set_lanes_per_pose(lp)
+                print("case: quad-line vs pair-line bits, layout", layout, "split", lp, flush=True)
+                dk.dock_score_set_split(lp)
                 got[layout, lp] = _gpu_energies(dk, pocket, ligs, g)
     finally:
-        dk.dock_score_set_lanes_per_pose(0)
+        dk.dock_score_set_split(0)
     for lp in (1, 2, 4):
         assert np.array_equal(got[3, lp].view(np.uint32), got[4, lp].view(np.uint32)), lp
     assert np.isfinite(got[4, 1]).all()
@@ -200,10 +200,10 @@ def test_deterministic_across_calls(dk):
     assert np.array_equal(a, b, equal_nan=True)
 
 
-def test_lanes_per_pose_same_bits(dk, ora):
-    """Every scoring launch shape (1, 2 or 4 lanes per pose) gives the same bits,
-    on ligands of 1-96 atoms mixed across wavefronts with a ragged pose count;
-    the one-lane shape also matches the oracle."""
+def test_split_same_bits(dk, ora):
+    """Every scoring launch shape (1, 2 or 4 wavefronts per block of 64 poses)
+    gives the same bits, on ligands of 1-96 atoms mixed within blocks with a
+    ragged pose count; the one-wavefront shape also matches the oracle."""
     ff, rec, grid, maps = system(2, grid_n=48, solpar=-0.0011, hbond=True)
     sizes = [(1, 0), (7, 1), (24, 6), (40, 10), (61, 12), (96, 20)]
     ligands = [synth.make_ligand(4, i, a, t, 8) for i, (a, t) in enumerate(sizes)]
@@ -220,12 +220,12 @@ def test_lanes_per_pose_same_bits(dk, ora):
     runs = {}
     try:
         for lp in (1, 2, 4):
-            print("case: scoring lanes per pose", lp, flush=True)
-            dk.dock_score_set_lanes_per_pose(lp)
-            assert dk.dock_score_lanes_per_pose(ligs) == lp
+            print("case: scoring split", lp, flush=True)
+            dk.dock_score_set_split(lp)
+            assert dk.dock_score_split(ligs) == lp
             runs[lp] = _gpu_energies(dk, pocket, ligs, g, pl)
     finally:
-        dk.dock_score_set_lanes_per_pose(0)
+        dk.dock_score_set_split(0)
     np.testing.assert_array_equal(runs[2], runs[1])
     np.testing.assert_array_equal(runs[4], runs[1])
     sub = np.arange(0, n, 7)
@@ -233,36 +233,32 @@ def test_lanes_per_pose_same_bits(dk, ora):
     keep = near_face_mask(ora, grid, ligands, g[sub], pl[sub])
     assert_energies_match(runs[1][sub], e_ref, keep)
     with pytest.raises(dk.DockError):
-        dk.dock_score_set_lanes_per_pose(3)
+        dk.dock_score_set_split(3)
 
 
-def test_automatic_lanes_per_pose_follow_layout_and_size(dk):
-    """The automatic scoring shape depends on the set's largest ligand and the
-    pocket's map layout: with pair-line maps two lanes up to 40 atoms and four
-    above; with the other layouts one lane up to 32 atoms, two up to 40, four
-    above.  A fixed setting overrides it and 0 restores it."""
+def test_automatic_split(dk):
+    """The automatic scoring split is four wavefronts per block of 64 poses for
+    every ligand size and map layout (the fastest at every size measured); a
+    fixed setting overrides it and 0 restores it."""
     ff, rec, grid, maps = system(0)
-    cases = {dk.DOCK_LAYOUT_PAIRLINE: {24: 2, 40: 2, 41: 4, 96: 4},
-             dk.DOCK_LAYOUT_QUADLINE: {24: 1, 32: 1, 40: 2, 41: 4},
-             dk.DOCK_LAYOUT_ZPAIR: {32: 1, 33: 2, 48: 4}}
-    dk.dock_score_set_lanes_per_pose(0)
-    for layout, by_size in cases.items():
+    dk.dock_score_set_split(0)
+    for layout in (dk.DOCK_LAYOUT_PAIRLINE, dk.DOCK_LAYOUT_QUADLINE, dk.DOCK_LAYOUT_ZPAIR):
         pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
-        for atoms, want in by_size.items():
+        for atoms in (5, 16, 40, 96):
             ligs = dk.dock_create_ligands(pocket, [synth.make_ligand(1, 900 + atoms, 12, 2, 8),
-                                                   synth.make_ligand(1, atoms, atoms, 4, 8)])
-            assert dk.dock_score_lanes_per_pose(ligs) == want, (layout, atoms)
+                                                   synth.make_ligand(1, atoms, atoms, 3, 8)])
+            assert dk.dock_score_split(ligs) == 4, (layout, atoms)
     try:
-        dk.dock_score_set_lanes_per_pose(1)
-        assert dk.dock_score_lanes_per_pose(ligs) == 1
+        dk.dock_score_set_split(1)
+        assert dk.dock_score_split(ligs) == 1
     finally:
-        dk.dock_score_set_lanes_per_pose(0)
-    assert dk.dock_score_lanes_per_pose(ligs) == 4
+        dk.dock_score_set_split(0)
+    assert dk.dock_score_split(ligs) == 4
 
 
 def test_max_torsions_and_types(dk, ora):
     """The limits of the ABI at once: 32 atom types (34 maps) and a ligand with
-    32 torsions (39 genes), for every map layout and lanes-per-pose shape, plus
+    32 torsions (39 genes), for every map layout and scoring split, plus
     the DE trial of a 39-gene genotype bit for bit against the oracle."""
     import torch
     import oracle
@@ -282,11 +278,11 @@ def test_max_torsions_and_types(dk, ora):
             pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
             ligs = dk.dock_create_ligands(pocket, [lig])
             for lp in (1, 2, 4):
-                print("case: 32 types, 32 torsions, layout", layout, "lanes", lp, flush=True)
-                dk.dock_score_set_lanes_per_pose(lp)
+                print("case: 32 types, 32 torsions, layout", layout, "split", lp, flush=True)
+                dk.dock_score_set_split(lp)
                 assert_energies_match(_gpu_energies(dk, pocket, ligs, g), e_ref, keep)
     finally:
-        dk.dock_score_set_lanes_per_pose(0)
+        dk.dock_score_set_split(0)
     P = 40
     params = dict(pop_size=P, n_generations=1, seed=9, box_lo=tuple(lo), box_hi=tuple(hi))
     pop = ora.de_init(lig, ora.SearchParams(**params), 0, 39)[None]

@@ -268,6 +268,26 @@ dock_status dock_search(const dock_pocket *pocket, const dock_ligands *ligs, con
                         int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                         float *best_energies, const float *target, int32_t *gen_reached, void *stream);
 
+/* The same search as dock_search, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It allocates nothing: its scratch (the bucket queue
+ * counters, the trials and the gene-major population copy) lives in one fixed
+ * area of DOCK_NO_ALLOC_SCRATCH_BYTES per device, reserved when the library's
+ * device code is loaded on that device and held until the process ends.  The
+ * area holds 256 bytes of counters and two arrays of n_ligands x pop_size x
+ * g_stride floats, each rounded up to 256 bytes; a larger search is rejected
+ * with DOCK_E_INVALID before anything is enqueued.  The size buckets run one
+ * after another on stream (no side streams, no events), so results are the
+ * same bits as dock_search's and only the overlap of buckets is lost.  Every
+ * call on a device shares that device's area, which keeps the last call's
+ * contents: calls that overlap on one device (on different streams, or from
+ * different threads) race and give undefined results; calls ordered on one
+ * stream are safe.  Arguments, in/out buffers and other errors as dock_search. */
+#define DOCK_NO_ALLOC_SCRATCH_BYTES (64u << 20)
+dock_status dock_search_no_alloc(const dock_pocket *pocket, const dock_ligands *ligs, const dock_search_params *params,
+                                 int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
+                                 float *best_energies, const float *target, int32_t *gen_reached, void *stream);
+
 /* ---- Search plans: one captured graph per search -------------------------------
  * A plan holds its own scratch (trials and the gene-major population copy,
  * 2 x n_ligands x pop_size x g_stride floats, and the bucket queues) and the

@@ -821,12 +821,30 @@ static SearchShape bucket_shape(const dock_pocket *p, const LigandBucket &B, int
 // handle's side streams (forked from and joined back to s), so that small
 // buckets do not leave the GPU idle while the last ligands of another finish.
 // Costliest bucket first, each onto the side stream with the least work so far,
-// so the longest bucket never waits behind another.
+// so the longest bucket never waits behind another.  With serial set, the
+// buckets run one after another on s instead (the same order, no side streams
+// and no events).
 static hipError_t search_pass(const dock_pocket *p, const dock_ligands *L, SearchLaunch S, int32_t *queues,
-                              hipStream_t s, const char **step) {
+                              hipStream_t s, const char **step, bool serial) {
   const int nb = (int)L->buckets.size();
   *step = "queue reset";
   hipError_t e = launch_fill_i32(queues, nb, 0, s);
+  if (serial) {
+    int by_cost[DOCK_SEARCH_BUCKETS];
+    int m = 0;
+    for (int b = 0; b < nb && m < DOCK_SEARCH_BUCKETS; ++b)
+      if (L->buckets[b].count > 0) by_cost[m++] = b;
+    std::stable_sort(by_cost, by_cost + m, [&](int x, int y) { return L->buckets[x].cost > L->buckets[y].cost; });
+    for (int k = 0; k < m && e == hipSuccess; ++k) {
+      const LigandBucket &B = L->buckets[by_cost[k]];
+      S.order = L->order + B.offset;
+      S.n_order = B.count;
+      S.queue = queues + by_cost[k];
+      S.lds_atoms = B.lds_atoms;
+      e = launch_search(S, p->layout, p->n_cu, bucket_shape(p, B, S.p.pop), s, step);
+    }
+    return e;
+  }
   std::lock_guard<std::mutex> guard(L->side_mu);
   if (e == hipSuccess) *step = "side streams", e = L->ensure_side_streams();
   hipEvent_t fork = nullptr;
@@ -902,7 +920,7 @@ struct SearchScratch {
 static hipError_t enqueue_search(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
                                  int32_t g_stride, float *population, float *pop_energy, float *best_genotypes,
                                  float *best_energies, const float *target, int32_t *gen_reached,
-                                 const SearchScratch &X, hipStream_t s, const char **step) {
+                                 const SearchScratch &X, hipStream_t s, const char **step, bool serial = false) {
   const bool track = target && gen_reached;
   const dock_mlp *net = q->proposal;
   const int P = q->pop_size;
@@ -923,7 +941,7 @@ static hipError_t enqueue_search(const dock_pocket *p, const dock_ligands *L, co
   S.stop = q->stop_at_target ? 1 : 0;
   S.trials = X.trials;
   S.work = X.work;
-  if (!net) return search_pass(p, L, S, X.queues, s, step);
+  if (!net) return search_pass(p, L, S, X.queues, s, step, serial);
   // Learned proposals: a round fills the trial buffer with one proposal per
   // individual; the next persistent pass scores them and takes each greedily
   // before its generations (the pass's DE trials reuse that buffer afterwards).
@@ -940,7 +958,7 @@ static hipError_t enqueue_search(const dock_pocket *p, const dock_ligands *L, co
     // the initial population and its scores, then the first round
     SearchLaunch T = S;
     T.p.n_gen = 0;
-    e = search_pass(p, L, T, X.queues, s, step);
+    e = search_pass(p, L, T, X.queues, s, step, serial);
     if (e == hipSuccess) e = propose(g0);
     pending = true;
   } else if (every > 0 && g0 > 0 && g0 % every == 0 && g0 < q->proposal_until && g0 < g_end) {
@@ -962,7 +980,7 @@ static hipError_t enqueue_search(const dock_pocket *p, const dock_ligands *L, co
     T.p.first_gen = g;
     T.p.n_gen = seg_end - g;
     T.proposals = pending ? S.trials : nullptr;
-    e = search_pass(p, L, T, X.queues, s, step);
+    e = search_pass(p, L, T, X.queues, s, step, serial);
     pending = false;
     g = seg_end;
     if (g >= g_end) break;
@@ -993,6 +1011,69 @@ extern "C" dock_status dock_search(const dock_pocket *p, const dock_ligands *L, 
   if (X.queues) (void)hipFreeAsync(X.queues, s);
   if (X.work) (void)hipFreeAsync(X.work, s);
   if (X.trials) (void)hipFreeAsync(X.trials, s);
+  if (e != hipSuccess) return hip_err(e, step);
+  return DOCK_OK;
+}
+
+// ------------------------------------------------------------------------------ search without allocation
+// The fixed scratch of dock_search_no_alloc, one copy per device: 256 bytes of
+// bucket queue counters, then the trials and the gene-major population, each
+// rounded up to 256 bytes.  In host code `scratch` only names the array; its
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[DOCK_NO_ALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr size_t kScratchQueueBytes = 256;
+static_assert(DOCK_SEARCH_BUCKETS * sizeof(int32_t) <= kScratchQueueBytes, "queue counters fit their slot");
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Device address of this device's scratch (the device current).
+hipError_t scratch_address(int device, unsigned char **out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = (unsigned char *)ptr;
+  *out = (unsigned char *)ptr;
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" dock_status dock_search_no_alloc(const dock_pocket *p, const dock_ligands *L, const dock_search_params *q,
+                                           int32_t g_stride, float *population, float *pop_energy,
+                                           float *best_genotypes, float *best_energies, const float *target,
+                                           int32_t *gen_reached, void *stream) {
+  dock_status st = check_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target,
+                                gen_reached);
+  if (st) return st;
+  const size_t nf = (size_t)L->n_ligs * q->pop_size * g_stride;
+  const size_t arr = round256(sizeof(float) * nf);
+  if (nf > ((size_t)DOCK_NO_ALLOC_SCRATCH_BYTES - kScratchQueueBytes) / (2 * sizeof(float)) ||
+      kScratchQueueBytes + 2 * arr > (size_t)DOCK_NO_ALLOC_SCRATCH_BYTES)
+    return set_err(DOCK_E_INVALID,
+                   "search needs %zu bytes of scratch (n_ligands x pop_size x g_stride = %zu floats, twice), more "
+                   "than the fixed %u of dock_search_no_alloc",
+                   kScratchQueueBytes + 2 * arr, nf, (unsigned)DOCK_NO_ALLOC_SCRATCH_BYTES);
+  DeviceScope ds(p->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  unsigned char *base = nullptr;
+  HIP_TRY(scratch_address(p->device, &base), "hipGetSymbolAddress(scratch)");
+  SearchScratch X;
+  X.queues = (int32_t *)base;
+  X.trials = (float *)(base + kScratchQueueBytes);
+  X.work = (float *)(base + kScratchQueueBytes + arr);
+  const char *step = "search";
+  hipError_t e = enqueue_search(p, L, q, g_stride, population, pop_energy, best_genotypes, best_energies, target,
+                                gen_reached, X, (hipStream_t)stream, &step, true);
   if (e != hipSuccess) return hip_err(e, step);
   return DOCK_OK;
 }

@@ -82,6 +82,7 @@ _SIGS = {
     "dock_de_init": [_P, _P, C.c_int32, _P, _P],
     "dock_de_trials": [_P, _P, C.c_int32, C.c_int32, _P, _P, _P],
     "dock_search": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
+    "dock_search_no_alloc": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
     "dock_gather_probe": [_P, _P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, _P, _P],
     "dock_pair_probe": [_P, C.c_int64, C.c_int32, _P, _P],
     "dock_search_plan_create": [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P],
@@ -106,6 +107,7 @@ _SIGS = {
 }
 DOCK_MLP_IN, DOCK_MLP_HIDDEN, DOCK_MLP_OUT, DOCK_MLP_PARAMS, DOCK_DESC = 96, 256, 32, 98848, 64
 DOCK_MLP_MAX_BATCH = 65536
+DOCK_NO_ALLOC_SCRATCH_BYTES = 64 << 20
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -356,6 +358,15 @@ def dock_search(pocket: Pocket, ligs: Ligands, params: SearchParams, population,
     args = _search_buffers(pocket, ligs, params, population, pop_energy, best_genotypes, best_energies, target,
                            gen_reached)
     _check(_lib.dock_search(pocket.handle, ligs.handle, C.byref(P), *args, _stream(stream)))
+
+
+def dock_search_no_alloc(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy,
+                         best_genotypes, best_energies, target=None, gen_reached=None, stream=None):
+    """dock_search on the library's fixed per-device scratch (no allocation)."""
+    P = params._c()
+    args = _search_buffers(pocket, ligs, params, population, pop_energy, best_genotypes, best_energies, target,
+                           gen_reached)
+    _check(_lib.dock_search_no_alloc(pocket.handle, ligs.handle, C.byref(P), *args, _stream(stream)))
 
 
 def _search_buffers(pocket: Pocket, ligs: Ligands, params: SearchParams, population, pop_energy, best_genotypes,

@@ -32,7 +32,9 @@ import synth  # noqa: E402
 METRIC = "poses scored/sec (FP32, vs FP64 oracle) + time-to-target score, plain vs learned"
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 vector FMA without packed instructions (the library is built without
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per pose
 BYTES_PER_ATOM = 96            # 3 maps x 8 corners x 4 B gathered per atom
@@ -99,11 +101,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(n_poses: int):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary (scaled by the copy-kernel calibration), or None if the kernel has
-    changed since it was taken or the workload differs."""
-    path = os.path.join(ROOT, "profiles", "score_kernel_config1_traffic.txt")
+def read_record(name: str, n_poses: int):
+    """The key = value lines of a committed counter summary under profiles/, or
+    None if it is missing, was taken on other scoring-kernel code (its
+    kernel_hash) or on another workload (its poses)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -113,7 +115,39 @@ def recorded_traffic(n_poses: int):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_hash") != kernel_source_hash() or int(kv.get("poses", "0")) != n_poses:
         return None
-    return float(kv["traffic_bytes"])
+    return kv
+
+
+def recorded_traffic(n_poses: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (scaled by the copy-kernel calibration), or None if the kernel has
+    changed since it was taken or the workload differs."""
+    kv = read_record("score_kernel_config1_traffic.txt", n_poses)
+    return None if kv is None else float(kv["traffic_bytes"])
+
+
+def recorded_valu(n_poses: int):
+    """VALU activity of the scoring kernel from the committed rocprofv3 summary
+    (VALUBusy: the share of SIMD cycles issuing vector instructions, and the
+    same counter on the pair probe, a VALU-only kernel at full occupancy), or
+    None as for the traffic record."""
+    kv = read_record("score_kernel_config1_valu.txt", n_poses)
+    if kv is None:
+        return None
+    return {"valu_busy": float(kv["valu_busy"]), "valu_busy_pair_probe": float(kv["valu_busy_pair_probe"]),
+            "valu_share_of_probe": round(float(kv["valu_busy"]) / float(kv["valu_busy_pair_probe"]), 4),
+            "valu_utilization": float(kv["valu_utilization"]),
+            "valu_insts_per_pose": float(kv["valu_insts_per_pose"])}
+
+
+def choose_bound(traffic_frac, valu):
+    """The resource the counters say binds: HBM when the line traffic actually
+    moved is the larger share of the HBM peak, VALU when the kernel's VALUBusy
+    is the larger share of the pair probe's (a VALU-only kernel at full
+    occupancy, taken as a saturated VALU).  None unless both records apply."""
+    if traffic_frac is None or valu is None:
+        return None
+    return "alu" if valu["valu_busy"] / valu["valu_busy_pair_probe"] > traffic_frac else "hbm"
 
 
 def probes(S, kernel_ms: float, n_poses: int):
@@ -574,8 +608,13 @@ def main():
         dst.copy_(src)
         step()
         step()
+        # the two probes once each, as counter references
+        out = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
+        dk.dock_pair_probe(S["pocket"], out, 1024)
+        blo, bhi = synth.pocket_box(S["grid"])
+        dk.dock_gather_probe(S["pocket"], S["ligs"], 0, blo, bhi, out[:1 << 19], 128, in_flight=4)
         torch.cuda.synchronize()
-        log("profile run: 1 GiB copy, 2 scoring steps")
+        log("profile run: 1 GiB copy, 2 scoring steps, pair probe, gather probe")
         return
 
     for _ in range(args.warmup):
@@ -604,17 +643,26 @@ def main():
     flops_per_launch = FLOPS_PER_PAIR * S["n_pairs"] * n
     tflops = flops_per_launch / (kernel_ms * 1e-3) / 1e12
     traffic = recorded_traffic(n)
-    roofline = {"bound": "hbm", "achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gather_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+    traffic_frac = None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    valu = recorded_valu(n)
+    bound = choose_bound(traffic_frac, valu)
+    hbm_leg = {"achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gather_gbs / HBM_PEAK_GBS, 4)}
+    alu_leg = {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    measured = probes(S, kernel_ms, n)
+    roofline = {"bound": bound or "hbm", **(alu_leg if bound == "alu" else hbm_leg), "traffic": traffic,
+                "bound_source": "counters (line traffic vs VALUBusy)" if bound else
+                                "none: no counter record for this kernel code",
                 # the measured line traffic as a rate: what the fabric actually moves
                 "traffic_GBs": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
-                "traffic_frac": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_frac": None if traffic_frac is None else round(traffic_frac, 4),
+                "valu": valu,
+                "gather_probe_frac": measured["gather"]["frac"],
                 "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
                 "split": S["dk"].dock_score_split(S["ligs"]),
                 "kernel_ms_sd": round(float(np.std(step_ms)), 4), "kernel_ms_min": round(float(np.min(step_ms)), 4),
-                "alu": {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},
-                "measured": probes(S, kernel_ms, n)}
+                "hbm": hbm_leg, "alu": alu_leg, "measured": measured}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,

@@ -157,17 +157,19 @@ typedef struct {
   const float *xyz;             /* [n_atoms][3] reference conformation */
   const int32_t *type;          /* [n_atoms] in [0, n_types) */
   const float *charge;          /* [n_atoms] */
-  const int32_t *bonds;         /* [n_atoms-1][2]; must form a tree: a ring is DOCK_E_UNSUPPORTED */
+  const int32_t *bonds;         /* [n_atoms-1][2] distinct bonds that must form a tree: bonds that
+                                   close a ring (and so leave some atom unconnected) are
+                                   DOCK_E_UNSUPPORTED; a repeated or self bond is DOCK_E_INVALID */
   const int32_t *torsion_bonds; /* [n_torsions] distinct indices into bonds, neither end of degree 1 */
 } dock_ligand_desc;
 
 /* Preprocess a ligand set for a pocket: root at atom 0, ligand origin at the
  * centroid of the reference conformation, intra pairs = atom pairs at least four
  * bonds apart that lie in different rigid fragments (Algorithm 2's pair loop; no
- * distance cutoff).  Errors: DOCK_E_INVALID (bonds out of range or not
- * connecting all atoms, torsion on a terminal or repeated bond, type out of
- * range, non-finite input, n_ligands < 1), DOCK_E_UNSUPPORTED (> 96 atoms, > 32
- * torsions, bonds that close a ring), DOCK_E_NOMEM, DOCK_E_DEVICE. */
+ * distance cutoff).  Errors: DOCK_E_INVALID (bonds out of range, repeated or
+ * joining an atom to itself, torsion on a terminal or repeated bond, type out
+ * of range, non-finite input, n_ligands < 1), DOCK_E_UNSUPPORTED (> 96 atoms,
+ * > 32 torsions, bonds that close a ring), DOCK_E_NOMEM, DOCK_E_DEVICE. */
 dock_status dock_create_ligands(const dock_pocket *pocket, const dock_ligand_desc *ligands,
                                 int32_t n_ligands, dock_ligands **out);
 

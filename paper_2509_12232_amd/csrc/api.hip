@@ -399,12 +399,29 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
     if (!isfinite(d.xyz[3 * i]) || !isfinite(d.xyz[3 * i + 1]) || !isfinite(d.xyz[3 * i + 2]) || !isfinite(d.charge[i]))
       return set_err(DOCK_E_INVALID, "ligand %d: non-finite coordinate or charge", lig);
   }
+  // n - 1 distinct bonds form a tree exactly when none of them closes a cycle
+  // (union-find); a repeated bond is invalid, a cycle is a ring
   std::vector<std::vector<int>> adj(n);
-  for (int k = 0; k < n - 1; ++k) {
-    const int a = d.bonds[2 * k], b = d.bonds[2 * k + 1];
-    if (a < 0 || a >= n || b < 0 || b >= n || a == b) return set_err(DOCK_E_INVALID, "ligand %d: bad bond %d", lig, k);
-    adj[a].push_back(b);
-    adj[b].push_back(a);
+  {
+    std::vector<int> comp(n);
+    std::iota(comp.begin(), comp.end(), 0);
+    auto find = [&](int x) {
+      while (comp[x] != x) x = comp[x] = comp[comp[x]];
+      return x;
+    };
+    for (int k = 0; k < n - 1; ++k) {
+      const int a = d.bonds[2 * k], b = d.bonds[2 * k + 1];
+      if (a < 0 || a >= n || b < 0 || b >= n || a == b)
+        return set_err(DOCK_E_INVALID, "ligand %d: bad bond %d", lig, k);
+      if (std::find(adj[a].begin(), adj[a].end(), b) != adj[a].end())
+        return set_err(DOCK_E_INVALID, "ligand %d: repeated bond %d", lig, k);
+      const int ra = find(a), rb = find(b);
+      if (ra == rb)
+        return set_err(DOCK_E_UNSUPPORTED, "ligand %d: the bonds close a ring (rings are not supported)", lig);
+      comp[ra] = rb;
+      adj[a].push_back(b);
+      adj[b].push_back(a);
+    }
   }
   // depth-first pre-order from the root
   std::vector<int> parent(n, -1), order, pos(n, -1), size(n, 1);

@@ -32,3 +32,23 @@ def test_recorded_traffic_applies_to_its_workload_only(monkeypatch):
 def test_recorded_traffic_refuses_a_changed_kernel(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
     assert bench.recorded_traffic(10_000_000) is None
+
+
+def test_valu_record_applies_to_its_kernel_only(monkeypatch):
+    import os
+    path = os.path.join(bench.ROOT, "profiles", "score_kernel_config1_valu.txt")
+    h = [ln.split("=", 1)[1].strip() for ln in open(path) if ln.startswith("kernel_hash")][0]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    v = bench.recorded_valu(10_000_000)
+    assert v is not None and 0 < v["valu_busy_pair_probe"] and 0 < v["valu_busy"]
+    assert bench.recorded_valu(10_000_001) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.recorded_valu(10_000_000) is None
+
+
+def test_bound_follows_the_larger_counter_share():
+    v = {"valu_busy": 1.2, "valu_busy_pair_probe": 1.1, "valu_utilization": 1.0, "valu_insts_per_pose": 400.0}
+    assert bench.choose_bound(0.8, v) == "alu"     # 1.2 / 1.1 of the probe's busy share
+    assert bench.choose_bound(1.1, v) == "hbm"
+    assert bench.choose_bound(None, v) is None
+    assert bench.choose_bound(0.5, None) is None

@@ -187,6 +187,28 @@ def test_empty_batch_and_invalid_args(dk):
         dk.dock_create_ligands(pocket, [too_big])
 
 
+def test_ring_is_unsupported(dk):
+    """Bonds that close a ring are valid chemistry outside what this build
+    supports (the rotatable-bond tree of Algorithm 1): DOCK_E_UNSUPPORTED,
+    wherever the ring lies.  A repeated bond is invalid input."""
+    import dataclasses
+    ff, rec, grid, maps = system(0)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    lig = synth.make_ligand(1, 0, 6, 0, 8)
+    for bonds in ([[0, 1], [1, 2], [2, 3], [3, 0], [4, 5]],    # ring through the root atom
+                  [[0, 1], [1, 2], [3, 4], [4, 5], [5, 3]]):   # ring apart from it
+        ring = dataclasses.replace(lig, bonds=np.array(bonds, np.int32))
+        with pytest.raises(dk.DockError) as ei:
+            dk.dock_create_ligands(pocket, [ring])
+        assert ei.value.status == dk.DOCK_E_UNSUPPORTED and "ring" in str(ei.value), bonds
+    for bonds in ([[0, 1], [1, 2], [2, 3], [3, 4], [4, 3]], [[0, 1], [1, 2], [2, 2], [3, 4], [4, 5]]):
+        bad = dataclasses.replace(lig, bonds=np.array(bonds, np.int32))
+        with pytest.raises(dk.DockError) as ei:
+            dk.dock_create_ligands(pocket, [bad])
+        assert ei.value.status == dk.DOCK_E_INVALID, bonds
+    dk.dock_create_ligands(pocket, [lig])
+
+
 def test_deterministic_across_calls(dk):
     import torch
     ff, rec, grid, maps = system(0)

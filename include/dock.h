@@ -65,7 +65,9 @@ typedef struct dock_ligands dock_ligands;  /* preprocessed ligand set, on the po
  *   electrostatic: coulomb q_i q_j / (eps(r') r'),
  *               eps(r) = diel_A + (diel_eps0 - diel_A) / (1 + diel_k exp(-diel_lambda (diel_eps0 - diel_A) r))
  *   desolvation: (S_i vol_j + S_j vol_i) exp(-r'^2 / (2 sigma^2)), S = solpar + qsolpar |q|
- * map_cap clamps the maps built by dock_create_pocket_from_receptor. */
+ * e_cap (the cap on the repulsive term), r_min, sigma and map_cap must be
+ * positive and finite.  map_cap clamps the maps built by
+ * dock_create_pocket_from_receptor. */
 typedef struct {
   int32_t n_types;                          /* 1..32 */
   const float *Rii, *epsii, *vol, *solpar;  /* [n_types] */
@@ -196,7 +198,7 @@ dock_status dock_score_poses(const dock_pocket *pocket, const dock_ligands *ligs
 
 /* Launch shape of dock_score_poses (a tuning knob; energies are bit-identical
  * for every shape).  Poses are scored in blocks of 64, one per lane; split =
- * 1, 2 or 4 wavefronts build and score a block together, sharing its LDS (3
+ * 1, 2, 4 or 8 wavefronts build and score a block together, sharing its LDS (3
  * floats per atom per pose) and splitting each pose's atoms and pair records,
  * so more wavefronts stay resident for large ligands; 0 restores the automatic
  * choice by the set's largest ligand.  Process-wide; takes effect at the next
@@ -311,7 +313,7 @@ dock_status dock_search_plan_destroy(dock_search_plan *plan);
 /* ---- Launch shapes of the search and their autotuner --------------------------
  * dock_search runs one persistent kernel per ligand-size bucket (atom counts
  * up to 16, 32, 48, 64, 96); a workgroup runs one ligand's search at a time.
- * Its shape: the split (1, 2 or 4 wavefronts build and score a block of 64
+ * Its shape: the split (1, 2, 4 or 8 wavefronts build and score a block of 64
  * individuals together, splitting their atoms and pair records and sharing
  * the block's LDS) and blocks per workgroup (1 up to 12 / split, 0 = chosen at
  * launch from the ligand count and the LDS residency).  Energies, and hence
@@ -322,8 +324,8 @@ dock_status dock_search_plan_destroy(dock_search_plan *plan);
 #define DOCK_SEARCH_BUCKETS 5
 typedef struct {
   int32_t max_atoms;        /* the bucket's upper atom count (read-only: 16, 32, 48, 64, 96) */
-  int32_t split;            /* wavefronts per block of 64 individuals: 1, 2 or 4 */
-  int32_t blocks_per_group; /* 0..12 / split */
+  int32_t split;            /* wavefronts per block of 64 individuals: 1, 2, 4 or 8 */
+  int32_t blocks_per_group; /* 0..12 / split (0..1 for split 8) */
 } dock_search_shape;
 
 /* The handle's shapes, host dock_search_shape[DOCK_SEARCH_BUCKETS]: the
@@ -335,8 +337,8 @@ dock_status dock_search_shapes(const dock_ligands *ligs, dock_search_shape *shap
 dock_status dock_search_set_shapes(dock_ligands *ligs, const dock_search_shape *shapes);
 /* Autotuner: for every non-empty bucket, times a search of tune_generations
  * generations (params' pop_size, seed, box) of the bucket's ligands for every
- * shape (split 1, 2 and 4 x 1 up to 12 / split blocks, at most one block per
- * 64 individuals), warm-up run first,
+ * shape (split 1, 2, 4 and 8 x 1 up to 12 / split blocks, at most one block
+ * per 64 individuals), warm-up run first,
  * with HIP events on stream, and fixes the fastest.  Results are cached for the
  * process under (device architecture and compute-unit count, map layout and
  * dimensions, bucket, its largest ligand, pop_size); a cached bucket is not

@@ -169,7 +169,7 @@ static dock_status check_ff(const dock_forcefield *ff) {
     for (int b = 0; b < ff->n_types; ++b)
       if (ff->hbond[a * ff->n_types + b] > 1 || ff->hbond[a * ff->n_types + b] != ff->hbond[b * ff->n_types + a])
         return set_err(DOCK_E_INVALID, "hbond table must be symmetric 0/1");
-  if (!(ff->sigma > 0) || !(ff->r_min > 0) || !isfinite(ff->e_cap) || !isfinite(ff->coulomb) ||
+  if (!(ff->sigma > 0) || !(ff->r_min > 0) || !(ff->e_cap > 0) || !isfinite(ff->e_cap) || !isfinite(ff->coulomb) ||
       !isfinite(ff->diel_A) || !isfinite(ff->diel_eps0) || !isfinite(ff->diel_lambda) || !isfinite(ff->diel_k) ||
       !isfinite(ff->qsolpar) || !(ff->map_cap > 0))
     return set_err(DOCK_E_INVALID, "bad force-field constant");
@@ -528,10 +528,10 @@ dock_status prep_ligand(const dock_pocket *P, const dock_ligand_desc &d, int lig
   std::sort(hb.begin(), hb.end(), by_ij);
   o.n_plain = (int)plain.size();
   o.n_hb = (int)hb.size();
-  o.n_groups = (o.n_plain + 3) / 4;
-  // 12-6 pairs padded to whole groups of four, two spare all-zero groups, then 12-10 pairs
+  o.n_groups = (o.n_plain + kParts - 1) / kParts;
+  // 12-6 pairs padded to whole groups of kParts, two spare all-zero groups, then 12-10 pairs
   o.pairs = plain;
-  o.pairs.resize((size_t)4 * (o.n_groups + 2), PairRec{0, 0.f, 0.f, 0.f, 0.f});
+  o.pairs.resize((size_t)kParts * (o.n_groups + 2), PairRec{0, 0.f, 0.f, 0.f, 0.f});
   o.pairs.insert(o.pairs.end(), hb.begin(), hb.end());
   // descriptor: type fractions, torsion and atom counts, charge statistics,
   // radius of gyration of the reference conformation, pair count
@@ -592,7 +592,7 @@ extern "C" dock_status dock_create_ligands(const dock_pocket *pocket, const dock
     h.atom_off = (int)atoms.size();
     h.tor_off = (int)tors.size();
     h.pair_off = (int)pairs.size();
-    h.hb_off = h.pair_off + 4 * (o.n_groups + 2);
+    h.hb_off = h.pair_off + kParts * (o.n_groups + 2);
     pair_count[l] = o.n_plain + o.n_hb;
     if ((double)pairs.size() + o.pairs.size() > 2.0e9) return set_err(DOCK_E_UNSUPPORTED, "ligand set too large");
     atoms.insert(atoms.end(), o.atoms.begin(), o.atoms.end());
@@ -672,14 +672,14 @@ static std::atomic<int32_t> g_score_split{0};
 // shared by its wavefronts, so a larger split keeps more wavefronts resident
 // per CU for the same LDS, at the cost of the pose build's barriers and of the
 // per-torsion setup each wavefront repeats.  Measured on MI355X (fourteen
-// 100^3 maps in the pair-line layout, 4e6 random poses of one ligand of each
-// size), four wavefronts were the fastest at every size from 12 to 96 atoms:
-// within 3% of one up to 24 atoms, then 1.39x (32 atoms), 1.67x (40), 1.93x
-// (48), 2.06x (64) and 2.20x (96) faster than one.
+// 100^3 maps in the pair-line layout, 2e6 random poses of one ligand of each
+// size, M poses/s for splits 1 / 2 / 4 / 8): 12 atoms 4890 / 5057 / 5020 /
+// 3743; 24 atoms 2083 / 2387 / 2420 / 1931; 48 atoms 433 / 687 / 895 / 758;
+// 64 atoms 168 / 326 / 455 / 432; 96 atoms 51 / 113 / 165 / 200.  Four
+// wavefronts up to 64 atoms, eight above.
 static int32_t score_split_auto(int32_t max_atoms, int32_t layout) {
-  (void)max_atoms;
   (void)layout;
-  return 4;
+  return max_atoms > 64 ? 8 : 4;
 }
 
 static int32_t score_split(const dock_ligands *L, int32_t layout) {
@@ -688,8 +688,8 @@ static int32_t score_split(const dock_ligands *L, int32_t layout) {
 }
 
 extern "C" dock_status dock_score_set_split(int32_t split) {
-  if (split != 0 && split != 1 && split != 2 && split != 4)
-    return set_err(DOCK_E_INVALID, "split must be 0, 1, 2 or 4");
+  if (split != 0 && split != 1 && split != 2 && split != 4 && split != 8)
+    return set_err(DOCK_E_INVALID, "split must be 0, 1, 2, 4 or 8");
   g_score_split.store(split);
   return DOCK_OK;
 }
@@ -1185,7 +1185,8 @@ extern "C" dock_status dock_search_set_shapes(dock_ligands *L, const dock_search
   for (size_t b = 0; b < L->buckets.size(); ++b) {
     const dock_search_shape &x = shapes[b];
     if (x.max_atoms != L->buckets[b].upper) return set_err(DOCK_E_INVALID, "bucket %d bound must be %d", (int)b, L->buckets[b].upper);
-    if (x.split != 1 && x.split != 2 && x.split != 4) return set_err(DOCK_E_INVALID, "split must be 1, 2 or 4");
+    if (x.split != 1 && x.split != 2 && x.split != 4 && x.split != 8)
+      return set_err(DOCK_E_INVALID, "split must be 1, 2, 4 or 8");
     if (x.blocks_per_group < 0 || x.blocks_per_group * x.split * kWave > kSearchMaxThreads)
       return set_err(DOCK_E_INVALID, "blocks_per_group must be in 0..%d for split %d",
                      kSearchMaxThreads / (kWave * x.split), x.split);
@@ -1257,7 +1258,7 @@ extern "C" dock_status dock_search_autotune(const dock_pocket *p, dock_ligands *
     S.lds_atoms = B.lds_atoms;
     SearchShape best{0, 0};
     float best_ms = 0.f;
-    for (int ws = 1; ws <= 4 && e == hipSuccess; ws *= 2) {
+    for (int ws = 1; ws <= kMaxSplit && e == hipSuccess; ws *= 2) {
       const int max_b = std::min(kSearchMaxThreads / (kWave * ws), (P + kBlock - 1) / kBlock);
       for (int nb = 1; nb <= max_b && e == hipSuccess; ++nb) {
         const SearchShape shape{ws, nb};
@@ -1342,7 +1343,7 @@ extern "C" dock_status dock_search_tune_load(const char *path) {
     const bool valid = got == 12 && k.n_cu > 0 && k.layout >= kLinear && k.layout <= kPairLine && k.nx >= 2 &&
                        k.ny >= 2 && k.nz >= 2 && k.n_types >= 1 && k.n_types <= kMaxTypes && k.upper >= 1 &&
                        k.upper <= kMaxAtoms && k.lds_atoms >= 1 && k.lds_atoms <= k.upper && k.pop >= 4 &&
-                       (sh.split == 1 || sh.split == 2 || sh.split == 4) && sh.blocks >= 0 &&
+                       (sh.split == 1 || sh.split == 2 || sh.split == 4 || sh.split == 8) && sh.blocks >= 0 &&
                        sh.blocks * sh.split * kWave <= kSearchMaxThreads;
     if (!valid) {
       st = set_err(DOCK_E_INVALID, "%s line %d: not a search shape", path, n_line);

@@ -12,16 +12,21 @@ constexpr int kMaxTorsions = 32;
 constexpr int kMaxTypes = 32;
 constexpr int kWave = 64;
 constexpr int kBlock = kWave;   // poses per scoring block: one per lane
+// A pose's energy is the sum of kParts partial sums, each accumulated in a
+// fixed order and combined by a balanced tree; the 12-6 pair records come in
+// groups of kParts, record u of a group belonging to partial sum u.
+constexpr int kParts = 8;
+constexpr int kMaxSplit = 8;    // wavefronts sharing a block of poses: 1, 2, 4 or 8
 
 // Per ligand.  Atoms are renumbered in depth-first pre-order from the root
 // (atom 0), so every rotatable bond's moving fragment is one contiguous range.
-// Pairs: the 12-6 pairs in groups of four (the last group padded with records
+// Pairs: the 12-6 pairs in groups of kParts (the last group padded with records
 // whose coefficients are all zero, which contribute exactly 0), two further
 // all-zero groups that the kernel may prefetch past the end, then the 12-10 pairs.
 struct alignas(32) LigHeader {
   int32_t n_atoms;
   int32_t n_tors;
-  int32_t n_groups;    // groups of four 12-6 pair records
+  int32_t n_groups;    // groups of kParts 12-6 pair records
   int32_t n_pairs_hb;  // 12-10 pairs, starting at hb_off
   int32_t atom_off;    // into atoms[] / atom_type[]
   int32_t tor_off;     // into tors[]
@@ -126,7 +131,7 @@ struct ScoreLaunch {
   int64_t n_poses;
   float *energies;
   int32_t lds_atoms;           // atom slots per pose in LDS
-  int32_t split;               // wavefronts per block of 64 poses: 1, 2 or 4
+  int32_t split;               // wavefronts per block of 64 poses: 1, 2, 4 or 8
 };
 
 // Launchers (one translation unit per kernel family).

@@ -1,6 +1,6 @@
 // score.hip -- batched pose scoring kernel for gfx950.
 //
-// One workgroup of WS = 1, 2 or 4 wavefronts scores a block of 64 poses, one
+// One workgroup of WS = 1, 2, 4 or 8 wavefronts scores a block of 64 poses, one
 // per lane, the wavefronts splitting each pose's atoms and pair records (the
 // same bits for every WS).  Poses of one ligand share every uniform load; a
 // block holding poses of several ligands scores it once per ligand, each pass
@@ -12,8 +12,11 @@
 
 namespace dock {
 
+// With four or eight wavefronts per block the register budget is five
+// wavefronts per SIMD (96 VGPRs), which a block's LDS allows for ligands of up
+// to about 50 atoms.
 template <int LAYOUT, int WS>
-__global__ __launch_bounds__(kWave * WS) void score_kernel(ScoreLaunch A, int64_t first) {
+__global__ __launch_bounds__(kWave * WS, WS >= 4 ? 5 : 1) void score_kernel(ScoreLaunch A, int64_t first) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x % kWave;
   const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -37,8 +40,9 @@ __global__ __launch_bounds__(kWave * WS) void score_kernel(ScoreLaunch A, int64_
     const int leader = __ffsll((unsigned long long)todo) - 1;
     const int cur = __builtin_amdgcn_readlane(lig, leader);
     const LigHeader H = as_const(A.L.hdr)[cur];
-    // map loads two atoms ahead with one or two wavefronts per block (measured
-    // faster on MI355X; with four the extra registers cost more than they hide)
+    // map loads two atoms ahead with one or two wavefronts per block, one with
+    // four or eight (measured on MI355X: there the registers of a second atom
+    // cost more residency than its loads hide)
     const float v = score_pose<LAYOUT, WS, WS <= 2 ? 2 : 1>(A.L, A.geom, A.ff, A.maps, H, g, 1, my, red, h);
     if (valid && lig == cur) e = v;
     todo &= ~__ballot(valid && lig == cur);
@@ -72,6 +76,7 @@ static hipError_t launch_score_t(const ScoreLaunch &a, hipStream_t s) {
     case 1: return launch_score_ws<LAYOUT, 1>(a, s);
     case 2: return launch_score_ws<LAYOUT, 2>(a, s);
     case 4: return launch_score_ws<LAYOUT, 4>(a, s);
+    case 8: return launch_score_ws<LAYOUT, 8>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,11 +1,11 @@
 // score_pose.h -- device code that builds one pose from its genotype and scores
-// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one, two or four
+// it (Sec. V: Algorithm 1 followed by Algorithm 2), with one, two, four or eight
 // wavefronts sharing a block of poses.
 //
-// Mapping: a block of 64 poses, one per lane, is built and scored by WS = 1, 2
-// or 4 wavefronts together (the "split"): lane l of each of them works on pose
-// l, and wavefront h of the block takes its share of the atoms and of the pair
-// records.  All ligand data (atoms, torsions, pairs) is uniform across a
+// Mapping: a block of 64 poses, one per lane, is built and scored by WS = 1, 2,
+// 4 or 8 wavefronts together (the "split"): lane l of each of them works on
+// pose l, and wavefront h of the block takes its share of the atoms and of the
+// pair records.  All ligand data (atoms, torsions, pairs) is uniform across a
 // wavefront and arrives through scalar loads, so every loop below is a scalar
 // loop and every pair record is an instruction operand as loaded.  A pose's
 // atom coordinates live in an LDS column shared by its WS lanes: coordinate c
@@ -173,14 +173,19 @@ __device__ __forceinline__ Corners<LAYOUT> gather_corners(const MapGeom &G, cons
 // One non-bonded pair term.  hb selects the 12-10 attractive exponent.
 template <bool HB>
 __device__ __forceinline__ float pair_term(const FFConst &F, const PairRec &P, float dx, float dy, float dz) {
+  // The two clamps compare bit patterns as integers: that orders floats the
+  // way fmaxf / fminf do whenever the bound is positive (r2 and rmin2 are
+  // non-negative; a negative vdw is a negative integer, below any positive
+  // cap), and an integer max or min takes the scalar bound as an operand with
+  // no quieting step.
   float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  r2 = fmaxf(r2, F.rmin2);
+  r2 = __int_as_float(max(__float_as_int(r2), __float_as_int(F.rmin2)));
   const float ir = __builtin_amdgcn_rsqf(r2);
   const float ir2 = ir * ir;
   const float ir6 = ir2 * ir2 * ir2;
   const float ir12 = ir6 * ir6;
   const float att = HB ? ir6 * ir2 * ir2 : ir6;
-  const float vdw = fminf(fmaf(P.A, ir12, -P.B * att), F.e_cap);
+  const float vdw = __int_as_float(min(__float_as_int(fmaf(P.A, ir12, -P.B * att)), __float_as_int(F.e_cap)));
   const float r = r2 * ir;
   const float ex = __builtin_amdgcn_exp2f(r * F.diel_c);
   const float inv_eps = fmaf(F.k, ex, 1.f) * __builtin_amdgcn_rcpf(fmaf(F.Ak, ex, F.eps0));
@@ -207,9 +212,7 @@ __device__ __forceinline__ cptr<T> as_const(const T *p) {
   return (cptr<T>)p;
 }
 
-// The R records of one pair group that wavefront h of a WS-wavefront block
-// evaluates (records h R .. h R + R - 1 of the group's four, R = 4 / WS):
-// uniform, so they are scalar operands as loaded.
+// R consecutive pair records (uniform, so scalar operands as loaded).
 template <int R>
 struct PairSlice {
   PairRec r[R];
@@ -233,6 +236,17 @@ struct SliceCoords {
   }
 };
 
+// Balanced pairwise sum of N values (N a power of two): the order in which a
+// pose's partial sums are combined, the same for every split.
+template <int N>
+__device__ __forceinline__ float tree_sum(const float *v) {
+  if constexpr (N == 1) {
+    return v[0];
+  } else {
+    return tree_sum<N / 2>(v) + tree_sum<N / 2>(v + N / 2);
+  }
+}
+
 // Barrier of the wavefronts that share pose blocks (the workgroup), ordering
 // their LDS writes before the reads that follow.
 template <int WS>
@@ -248,21 +262,23 @@ __device__ __forceinline__ void block_sync() {
 // (each call holds n_tors + 3 workgroup barriers for WS > 1); lanes with no
 // pose of that ligand compute a value that the caller discards.
 //
-// Wavefront h owns the partial sums p_u for u in [h R, (h + 1) R), R = 4 / WS:
-//   p_u = inter over atoms i with i % 4 == u + record u of every pair group
-//         + 12-10 pairs p with p % 4 == u,
-// each summed in index order (inter first, then the groups, then the 12-10
-// pairs), and the energy is (p0 + p1) + (p2 + p3) for every WS, so the split
-// never changes a bit of the result.  Every wavefront returns the energy.
-// Non-finite genes give NaN.  AHEAD: how many pair slices ahead of its use an
-// atom's map loads are issued (more loads in flight, more registers); it does
-// not change the result.
+// The energy is the balanced pairwise sum of kParts = 8 partial sums p_u:
+//   p_u = (inter over atoms i with i % 8 == u, in index order)
+//       + (record u of every pair group, in group order, then the 12-10 pairs p
+//          with p % 8 == u, in index order),
+// and wavefront h owns p_u for u in [h R, (h + 1) R), R = 8 / WS.  Every split
+// therefore adds the same terms in the same order and gives the same bits.
+// Every wavefront returns the energy.  Non-finite genes give NaN.  AHEAD: how
+// many atoms ahead of its interpolation an atom's map loads are issued (more
+// loads in flight, more registers); it does not change the result.
 template <int LAYOUT, int WS, int AHEAD>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
                             const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my,
                             float *__restrict__ red, int h) {
-  static_assert(WS == 1 || WS == 2 || WS == 4, "one, two or four wavefronts per block");
-  constexpr int R = 4 / WS;   // partial sums (and records of a group) per wavefront
+  static_assert(WS == 1 || WS == 2 || WS == 4 || WS == 8, "one, two, four or eight wavefronts per block");
+  constexpr int R = kParts / WS;      // partial sums (and records of a group) per wavefront
+  constexpr int SL = R < 4 ? R : 4;   // records evaluated per step of the pair loop
+  constexpr int NP = R / SL;          // steps per pair group
   const int n = H.n_atoms;
   const cptr<float4> atoms = as_const(L.atoms) + H.atom_off;
   const cptr<int32_t> types = as_const(L.atom_type) + H.atom_off;
@@ -337,16 +353,18 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   // atom of slot k + AHEAD, then evaluates the k-th of equal slices of the pair
   // groups, then interpolates the atom of slot k from loads issued AHEAD
   // iterations earlier, so the pair arithmetic covers the latency of the
-  // gathers.  Within the pair loop, the coordinates of group g+1 and the records
-  // of group g+2 are requested before group g is evaluated (the list ends with
-  // spare zero groups to read past).
+  // gathers.  The wavefront's records form a stream of steps of SL records
+  // (NP steps per group); the coordinates of step s+1 and the records of step
+  // s+2 are requested before step s is evaluated (the list ends with spare zero
+  // groups to read past).
   const cptr<PairRec> pairs = as_const(L.pairs) + H.pair_off + h * R;
+  auto step_ptr = [&](int st) { return pairs + kParts * (st / NP) + (st % NP) * SL; };
   const int ng = H.n_groups;
-  // The wavefront's atoms in index order: slot k is atom 4 (k / R) + h R + k % R,
+  // The wavefront's atoms in index order: slot k is atom 8 (k / R) + h R + k % R,
   // of class h R + k % R; wavefront 0 has the most slots, the others skip their
   // last.
-  const int slots = R * (n / 4) + min(n % 4, R);
-  auto atom_of = [&](int slot) { return 4 * (slot / R) + h * R + slot % R; };
+  const int slots = R * (n / kParts) + min(n % kParts, R);
+  auto atom_of = [&](int slot) { return kParts * (slot / R) + h * R + slot % R; };
   float inter[R], intra[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) inter[u] = intra[u] = 0.f;
@@ -359,26 +377,30 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
 #pragma unroll
   for (int d = 0; d < AHEAD; ++d)
     if (d < slots) ring[d] = gather(d);
-  PairSlice<R> A, B;
-  A.load(pairs);
-  B.load(pairs + 4);
-  SliceCoords<R> X;
+  PairSlice<SL> A, B;
+  A.load(step_ptr(0));
+  B.load(step_ptr(1));
+  SliceCoords<SL> X;
   X.load(A, my);
   for (int k = 0; k < slots; ++k) {
     const int ka = k + AHEAD;
     if (ka < slots) ring[AHEAD] = gather(ka);
     const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
     for (int gi = g0; gi < g1; ++gi) {
-      SliceCoords<R> Xn;
-      Xn.load(B, my);
-      PairSlice<R> C;
-      C.load(pairs + 4 * (gi + 2));
 #pragma unroll
-      for (int u = 0; u < R; ++u)
-        intra[u] += pair_term<false>(F, A.r[u], X.xi[u] - X.xj[u], X.yi[u] - X.yj[u], X.zi[u] - X.zj[u]);
-      A = B;
-      B = C;
-      X = Xn;
+      for (int part = 0; part < NP; ++part) {
+        SliceCoords<SL> Xn;
+        Xn.load(B, my);
+        PairSlice<SL> C;
+        C.load(step_ptr(gi * NP + part + 2));
+#pragma unroll
+        for (int u = 0; u < SL; ++u)
+          intra[part * SL + u] +=
+              pair_term<false>(F, A.r[u], X.xi[u] - X.xj[u], X.yi[u] - X.yj[u], X.zi[u] - X.zj[u]);
+        A = B;
+        B = C;
+        X = Xn;
+      }
     }
     const float v = interpolate_corners<LAYOUT>(ring[0]);
     if (atom_of(k) < n) {
@@ -389,9 +411,9 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
 #pragma unroll
     for (int d = 0; d < AHEAD; ++d) ring[d] = ring[d + 1];
   }
-  // 12-10 pairs, four at a time (past the end: all-zero records, which add +0)
+  // 12-10 pairs, kParts at a time (past the end: all-zero records, which add +0)
   const cptr<PairRec> hb = as_const(L.pairs) + H.hb_off;
-  for (int p = 0; p < H.n_pairs_hb; p += 4) {
+  for (int p = 0; p < H.n_pairs_hb; p += kParts) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int q = p + h * R + u;
@@ -405,20 +427,16 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   float part[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) part[u] = inter[u] + intra[u];
-  float e;
-  if constexpr (WS == 1) {
-    e = (part[0] + part[1]) + (part[2] + part[3]);
-  } else {
-    // wavefront h's share, p_{2h} + p_{2h+1} (two wavefronts) or p_h (four),
-    // through LDS to every wavefront of the block, each adding them in the
-    // same order
-    red[h * kBlock] = WS == 2 ? part[0] + part[R - 1] : part[0];
+  // this wavefront's share (the subtree of its partial sums), then, through
+  // LDS, the shares of the block's wavefronts in the same tree
+  float e = tree_sum<R>(part);
+  if constexpr (WS > 1) {
+    red[h * kBlock] = e;
     block_sync<WS>();
-    if constexpr (WS == 2) {
-      e = red[0] + red[kBlock];
-    } else {
-      e = (red[0] + red[kBlock]) + (red[2 * kBlock] + red[3 * kBlock]);
-    }
+    float share[WS];
+#pragma unroll
+    for (int w = 0; w < WS; ++w) share[w] = red[w * kBlock];
+    e = tree_sum<WS>(share);
   }
   return bad ? __builtin_nanf("") : e;
 }

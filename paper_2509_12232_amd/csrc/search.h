@@ -52,7 +52,7 @@ __host__ __device__ constexpr size_t search_block_floats(int32_t lds_atoms, int3
   return ((size_t)lds_atoms * 3 + (ws > 1 ? ws : 0)) * kWave;
 }
 
-// Launch shape of a bucket: the split (1, 2 or 4 wavefronts per block of 64
+// Launch shape of a bucket: the split (1, 2, 4 or 8 wavefronts per block of 64
 // poses) and the blocks per workgroup (0: chosen from the ligand count and the
 // residency the LDS allows).
 struct SearchShape {

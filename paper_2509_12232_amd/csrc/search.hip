@@ -6,11 +6,12 @@
 // function of (seed, population, generation, ligand, individual).
 //
 // dock_search runs one persistent kernel per ligand-size bucket: each workgroup
-// (up to four wavefronts) takes the next ligand from a work queue (largest
-// first) and runs its whole search -- initial population, then per generation
-// all trials, their scores and the greedy selection -- with no other launch or
-// host round trip.  Steps without a pose use one lane per individual; scoring
-// uses LP = 1, 2 or 4 lanes per individual (the same bits for every LP).
+// takes the next ligand from a work queue (largest first) and runs its whole
+// search -- initial population, then per generation all trials, their scores
+// and the greedy selection -- with no other launch or host round trip.  Steps
+// without a pose use one lane per individual; scoring gives each individual a
+// lane in a block of 64 that 1, 2, 4 or 8 wavefronts build and score together
+// (the same bits for every split).
 #include <algorithm>
 
 #include "search.h"
@@ -294,8 +295,11 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
 // left.  Block b of the workgroup keeps its poses' coordinates in its own LDS
 // region of lds_atoms * 3 rows of 64 dwords, followed (WS > 1) by WS rows for
 // the energy reduction.
+// Register budget: at least four wavefronts per SIMD (128 VGPRs) with four or
+// eight wavefronts per block, whose LDS per wavefront allows that residency;
+// three otherwise.
 template <int LAYOUT, int WS>
-__global__ __launch_bounds__(kSearchMaxThreads) void search_kernel(SearchLaunch S) {
+__global__ __launch_bounds__(kSearchMaxThreads, WS >= 4 ? 4 : 3) void search_kernel(SearchLaunch S) {
   extern __shared__ float lds[];
   __shared__ int s_q;
   const int block = __builtin_amdgcn_readfirstlane((threadIdx.x / kWave) / WS), lane = threadIdx.x % kWave;
@@ -410,6 +414,7 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
 template <int LAYOUT>
 static hipError_t launch_search_ws(const SearchLaunch &S, int32_t n_cu, SearchShape shape, hipStream_t s,
                                    const char **step) {
+  if (shape.split == 8) return launch_search_t<LAYOUT, 8>(S, n_cu, shape.blocks, s, step);
   if (shape.split == 4) return launch_search_t<LAYOUT, 4>(S, n_cu, shape.blocks, s, step);
   if (shape.split == 2) return launch_search_t<LAYOUT, 2>(S, n_cu, shape.blocks, s, step);
   return launch_search_t<LAYOUT, 1>(S, n_cu, shape.blocks, s, step);

@@ -295,7 +295,7 @@ def dock_score_poses(pocket: Pocket, ligs: Ligands, genotypes, energies, pose_li
 
 
 def dock_score_set_split(split: int):
-    """Wavefronts per block of 64 poses of the scoring kernel (1, 2 or 4; 0 =
+    """Wavefronts per block of 64 poses of the scoring kernel (1, 2, 4 or 8; 0 =
     automatic), process-wide."""
     _check(_lib.dock_score_set_split(int(split)))
 

@@ -94,6 +94,7 @@ def test_tune_cache_file_roundtrip(tmp_path):
     assert "gfx950 256 3 80 80 80 12 32 32 150 4 2" in lines and rows[0] not in lines
     for bad in ("gfx950 256 3 80 80 80 12 32 32 150 3 1",     # split 3
                 "gfx950 256 3 80 80 80 12 32 32 150 4 4",     # 16 wavefronts per workgroup
+                "gfx950 256 3 80 80 80 12 32 32 150 8 2",     # 16 wavefronts per workgroup
                 "gfx950 256 3 80 80 80 12 32 40 150 2 1",     # largest ligand above the bucket
                 "gfx950 256 7 80 80 80 12 32 32 150 2 1",     # unknown layout
                 "gfx950 256 3 80 80 80 12 32 32 150 2",       # a field missing

@@ -63,13 +63,13 @@ def test_pair_line_gives_the_quad_line_bits(dk):
         for layout in (3, 4):
             pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
             ligs = dk.dock_create_ligands(pocket, [lig])
-            for lp in (1, 2, 4):
+            for lp in (1, 2, 4, 8):
                 print("case: quad-line vs pair-line bits, layout", layout, "split", lp, flush=True)
                 dk.dock_score_set_split(lp)
                 got[layout, lp] = _gpu_energies(dk, pocket, ligs, g)
     finally:
         dk.dock_score_set_split(0)
-    for lp in (1, 2, 4):
+    for lp in (1, 2, 4, 8):
         assert np.array_equal(got[3, lp].view(np.uint32), got[4, lp].view(np.uint32)), lp
     assert np.isfinite(got[4, 1]).all()
 
@@ -223,7 +223,7 @@ def test_deterministic_across_calls(dk):
 
 
 def test_split_same_bits(dk, ora):
-    """Every scoring launch shape (1, 2 or 4 wavefronts per block of 64 poses)
+    """Every scoring launch shape (1, 2, 4 or 8 wavefronts per block of 64 poses)
     gives the same bits, on ligands of 1-96 atoms mixed within blocks with a
     ragged pose count; the one-wavefront shape also matches the oracle."""
     ff, rec, grid, maps = system(2, grid_n=48, solpar=-0.0011, hbond=True)
@@ -241,7 +241,7 @@ def test_split_same_bits(dk, ora):
         g[p, 7 + ligands[pl[p]].n_torsions:] = 0
     runs = {}
     try:
-        for lp in (1, 2, 4):
+        for lp in (1, 2, 4, 8):
             print("case: scoring split", lp, flush=True)
             dk.dock_score_set_split(lp)
             assert dk.dock_score_split(ligs) == lp
@@ -250,6 +250,7 @@ def test_split_same_bits(dk, ora):
         dk.dock_score_set_split(0)
     np.testing.assert_array_equal(runs[2], runs[1])
     np.testing.assert_array_equal(runs[4], runs[1])
+    np.testing.assert_array_equal(runs[8], runs[1])
     sub = np.arange(0, n, 7)
     e_ref = ora.score_poses(grid, maps, ff, ligands, g[sub], pose_ligand=pl[sub])
     keep = near_face_mask(ora, grid, ligands, g[sub], pl[sub])
@@ -259,23 +260,24 @@ def test_split_same_bits(dk, ora):
 
 
 def test_automatic_split(dk):
-    """The automatic scoring split is four wavefronts per block of 64 poses for
-    every ligand size and map layout (the fastest at every size measured); a
-    fixed setting overrides it and 0 restores it."""
+    """The automatic scoring split follows the set's largest ligand (the fastest
+    measured at each size): four wavefronts per block of 64 poses up to 64
+    atoms, eight above, for every map layout; a fixed setting overrides it and
+    0 restores it."""
     ff, rec, grid, maps = system(0)
     dk.dock_score_set_split(0)
     for layout in (dk.DOCK_LAYOUT_PAIRLINE, dk.DOCK_LAYOUT_QUADLINE, dk.DOCK_LAYOUT_ZPAIR):
         pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
-        for atoms in (5, 16, 40, 96):
+        for atoms in (5, 16, 40, 64, 65, 96):
             ligs = dk.dock_create_ligands(pocket, [synth.make_ligand(1, 900 + atoms, 12, 2, 8),
                                                    synth.make_ligand(1, atoms, atoms, 3, 8)])
-            assert dk.dock_score_split(ligs) == 4, (layout, atoms)
+            assert dk.dock_score_split(ligs) == (4 if atoms <= 64 else 8), (layout, atoms)
     try:
         dk.dock_score_set_split(1)
         assert dk.dock_score_split(ligs) == 1
     finally:
         dk.dock_score_set_split(0)
-    assert dk.dock_score_split(ligs) == 4
+    assert dk.dock_score_split(ligs) == 8
 
 
 def test_max_torsions_and_types(dk, ora):
@@ -299,7 +301,7 @@ def test_max_torsions_and_types(dk, ora):
         for layout in (0, 1, 2, 3, 4):
             pocket = dk.dock_create_pocket(grid, maps, ff, layout=layout)
             ligs = dk.dock_create_ligands(pocket, [lig])
-            for lp in (1, 2, 4):
+            for lp in (1, 2, 4, 8):
                 print("case: 32 types, 32 torsions, layout", layout, "split", lp, flush=True)
                 dk.dock_score_set_split(lp)
                 assert_energies_match(_gpu_energies(dk, pocket, ligs, g), e_ref, keep)

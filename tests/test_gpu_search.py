@@ -220,8 +220,10 @@ def test_launch_shape_does_not_change_results(dk):
     bounds = [b for b, _, _ in dk.dock_search_shapes(ligs)]
     assert bounds == [16, 32, 48, 64, 96]
     ref = None
-    for lp in (1, 2, 4):
+    for lp in (1, 2, 4, 8):
         for w in (0, 1, 2, 3):
+            if w * lp > 12:
+                continue   # at most twelve wavefronts per workgroup
             dk.dock_search_set_shapes(ligs, [(b, lp, w) for b in bounds])
             got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
             if ref is None:
@@ -230,22 +232,22 @@ def test_launch_shape_does_not_change_results(dk):
                 assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (lp, w)
     dk.dock_search_autotune(pocket, ligs, params, stride, tune_generations=2)
     for b, lp, w in dk.dock_search_shapes(ligs):
-        assert lp in (1, 2, 4) and 1 <= w <= 12 // lp
+        assert lp in (1, 2, 4, 8) and 1 <= w <= 12 // lp
     got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
     for x, y in zip(ref, got):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
     with pytest.raises(dk.DockError):
         dk.dock_search_set_shapes(ligs, [(b, 3, 0) for b in bounds])
-    # stopping at a target: the same generations and bests with splits of one, two or four
+    # stopping at a target: the same generations and bests with splits of one, two, four or eight
     import torch
     target = torch.from_numpy(ref[3] + 0.1).cuda()
     reached = []
-    for lp in (1, 2, 4):
+    for lp in (1, 2, 4, 8):
         dk.dock_search_set_shapes(ligs, [(b, lp, 0) for b in bounds])
         stop = _params(dk, lo, hi, pop_size=75, n_generations=6, stop_at_target=1)
         r = _run_gpu_search(dk, pocket, ligs, stop, len(ligands), stride, target=target)
         reached.append((r[4].cpu().numpy(), r[3].cpu().numpy()))
-    for k in (1, 2):
+    for k in (1, 2, 3):
         np.testing.assert_array_equal(reached[0][0], reached[k][0])
         np.testing.assert_array_equal(reached[0][1], reached[k][1])
     assert np.all((reached[0][0] >= 0) & (reached[0][0] <= 6))
@@ -308,7 +310,7 @@ def test_tune_cache_file_applies_to_new_handles(dk, tmp_path):
         b = int(f[7])
         if (b in mine and int(f[2]) == pocket.layout and int(f[3]) == 48 and int(f[9]) == 75
                 and int(f[8]) == largest[b]):
-            lp = {1: 2, 2: 4, 4: 1}[int(f[10])]
+            lp = {1: 2, 2: 4, 4: 8, 8: 1}[int(f[10])]
             f[10], f[11] = str(lp), "1"
             want[b] = (lp, 1)
         edited.append(" ".join(f))

@@ -36,9 +36,15 @@ HBM_PEAK_GBS = 8000.0
 # them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 78.6
 
+# VALU lane-instruction issue: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz
+VALU_PEAK_T_PER_S = 256 * 64 * 2.4e9 / 1e12
+
 # Algorithmic work per pose
 BYTES_PER_ATOM = 96            # 3 maps x 8 corners x 4 B gathered per atom
 FLOPS_PER_PAIR = 38            # one 12-6 pair term (FMA = 2, transcendental = 1)
+# VALU lane-instructions the method needs per pose: per non-bonded pair (the
+# pair term), per atom (pose build and interpolation), per torsion
+VALU_PER_PAIR, VALU_PER_ATOM, VALU_PER_TORSION = 30, 60, 20
 
 
 # The paper's own figures, as context (it prints no throughput or time for the
@@ -148,6 +154,46 @@ def choose_bound(traffic_frac, valu):
     if traffic_frac is None or valu is None:
         return None
     return "alu" if valu["valu_busy"] / valu["valu_busy_pair_probe"] > traffic_frac else "hbm"
+
+
+def roofline_record(kernel_ms: float, n: int, n_atoms: int, n_pairs: int, n_tors: int) -> dict:
+    """The scoring kernel against its roofline for a launch of n poses of one
+    ligand: the HBM leg (algorithmic map bytes), the ALU leg (algorithmic VALU
+    lane-instructions, with the pair flops and the executed instructions beside
+    them), the line traffic from the counter record, and the bound the counters
+    name.  The top-level achieved / peak / frac are those of the bound's leg."""
+    s = kernel_ms * 1e-3
+    gather_gbs = BYTES_PER_ATOM * n_atoms * n / s / 1e9
+    tflops = FLOPS_PER_PAIR * n_pairs * n / s / 1e12
+    valu_per_pose = VALU_PER_PAIR * n_pairs + VALU_PER_ATOM * n_atoms + VALU_PER_TORSION * n_tors
+    valu_rate = valu_per_pose * n / s / 1e12
+    traffic = recorded_traffic(n)
+    traffic_frac = None if traffic is None else traffic / s / 1e9 / HBM_PEAK_GBS
+    valu = recorded_valu(n)
+    bound = choose_bound(traffic_frac, valu)
+    hbm_leg = {"achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gather_gbs / HBM_PEAK_GBS, 4)}
+    alu_leg = {"achieved": round(valu_rate, 2), "peak": round(VALU_PEAK_T_PER_S, 2), "unit": "T VALU lane-instr/s",
+               "frac": round(valu_rate / VALU_PEAK_T_PER_S, 4),
+               "work": f"{valu_per_pose} algorithmic VALU lane-instructions per pose ({VALU_PER_PAIR} per pair, "
+                       f"{VALU_PER_ATOM} per atom, {VALU_PER_TORSION} per torsion)",
+               "flops": {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}}
+    if valu is not None:
+        # what the kernel issues, from the counters (64 lanes per wavefront instruction)
+        ex = valu["valu_insts_per_pose"] * 64 * n / s / 1e12
+        alu_leg["executed"] = {"lane_instr_per_pose": round(valu["valu_insts_per_pose"] * 64, 1),
+                               "achieved": round(ex, 2), "frac": round(ex / VALU_PEAK_T_PER_S, 4)}
+    return {"bound": bound or "hbm", **{k: v for k, v in (alu_leg if bound == "alu" else hbm_leg).items()
+                                        if k in ("achieved", "peak", "unit", "frac")},
+            "traffic": traffic,
+            "bound_source": "counters (line traffic vs VALUBusy)" if bound else
+                            "none: no counter record for this kernel code",
+            # the measured line traffic as a rate: what the fabric actually moves
+            "traffic_GBs": None if traffic is None else round(traffic / s / 1e9, 1),
+            "traffic_frac": None if traffic_frac is None else round(traffic_frac, 4),
+            "valu": valu, "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4),
+            "hbm": hbm_leg, "alu": alu_leg}
 
 
 def probes(S, kernel_ms: float, n_poses: int):
@@ -638,31 +684,12 @@ def main():
     log(f"energies: finite {np.isfinite(e).mean():.4f}, median {np.median(e):.3f}, min {e.min():.3f}")
 
     n_atoms = S["lig"].n_atoms
-    bytes_per_launch = BYTES_PER_ATOM * n_atoms * n
-    gather_gbs = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    flops_per_launch = FLOPS_PER_PAIR * S["n_pairs"] * n
-    tflops = flops_per_launch / (kernel_ms * 1e-3) / 1e12
-    traffic = recorded_traffic(n)
-    traffic_frac = None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-    valu = recorded_valu(n)
-    bound = choose_bound(traffic_frac, valu)
-    hbm_leg = {"achieved": round(gather_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(gather_gbs / HBM_PEAK_GBS, 4)}
-    alu_leg = {"achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-               "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
     measured = probes(S, kernel_ms, n)
-    roofline = {"bound": bound or "hbm", **(alu_leg if bound == "alu" else hbm_leg), "traffic": traffic,
-                "bound_source": "counters (line traffic vs VALUBusy)" if bound else
-                                "none: no counter record for this kernel code",
-                # the measured line traffic as a rate: what the fabric actually moves
-                "traffic_GBs": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
-                "traffic_frac": None if traffic_frac is None else round(traffic_frac, 4),
-                "valu": valu,
-                "gather_probe_frac": measured["gather"]["frac"],
-                "kernel": "score_kernel", "kernel_ms": round(kernel_ms, 4), "layout": S["pocket"].layout,
-                "split": S["dk"].dock_score_split(S["ligs"]),
-                "kernel_ms_sd": round(float(np.std(step_ms)), 4), "kernel_ms_min": round(float(np.min(step_ms)), 4),
-                "hbm": hbm_leg, "alu": alu_leg, "measured": measured}
+    roofline = roofline_record(kernel_ms, n, n_atoms, S["n_pairs"], S["lig"].n_torsions)
+    roofline.update({"gather_probe_frac": measured["gather"]["frac"], "layout": S["pocket"].layout,
+                     "split": S["dk"].dock_score_split(S["ligs"]),
+                     "kernel_ms_sd": round(float(np.std(step_ms)), 4),
+                     "kernel_ms_min": round(float(np.min(step_ms)), 4), "measured": measured})
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,

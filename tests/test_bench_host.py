@@ -52,3 +52,24 @@ def test_bound_follows_the_larger_counter_share():
     assert bench.choose_bound(1.1, v) == "hbm"
     assert bench.choose_bound(None, v) is None
     assert bench.choose_bound(0.5, None) is None
+
+
+def test_roofline_record_names_the_bound_of_the_committed_records(monkeypatch):
+    """With the committed counter records of the scoring kernel's code and the
+    benchmark workload (1e7 poses of a 40-atom, 604-pair, 10-torsion ligand):
+    both resources are near their limits and the VALU's share is the larger, so
+    the headline leg is the ALU one; the HBM leg and the traffic sit beside it."""
+    import os
+    path = os.path.join(bench.ROOT, "profiles", "score_kernel_config1_valu.txt")
+    h = [ln.split("=", 1)[1].strip() for ln in open(path) if ln.startswith("kernel_hash")][0]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    r = bench.roofline_record(6.88, 10_000_000, 40, 604, 10)
+    assert r["bound"] == "alu" and r["unit"] == "T VALU lane-instr/s"
+    assert r["frac"] == r["alu"]["frac"] and 0.5 < r["frac"] < 1.0
+    assert r["achieved"] == round(20720 * 1e7 / 6.88e-3 / 1e12, 2)
+    assert 0.8 < r["traffic_frac"] < 1.0 and r["traffic"] > 3.84e10
+    assert r["hbm"]["unit"] == "GB/s" and r["alu"]["executed"]["frac"] > r["alu"]["frac"]
+    # other kernel code: no records, the HBM leg by default, said so
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    r = bench.roofline_record(6.88, 10_000_000, 40, 604, 10)
+    assert r["bound"] == "hbm" and r["traffic"] is None and r["bound_source"].startswith("none")

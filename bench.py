@@ -468,7 +468,7 @@ def learned_vs_plain():
     # training data and training
     t0 = time.perf_counter()
     snaps, fin = pr.plain_snapshots(B["pocket"], L_tr, P, stride, pr.SNAPSHOT_GENERATIONS)
-    x, t = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
+    x, t, _ = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
     del snaps
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t0
@@ -562,7 +562,7 @@ def schedule_sweep(seeds=(1, 2)):
     for L in (L_val, L_tr):
         dk.dock_search_autotune(B["pocket"], L, P, stride, tune_generations=3)
     snaps, fin = pr.plain_snapshots(B["pocket"], L_tr, P, stride, pr.SNAPSHOT_GENERATIONS)
-    x, t = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
+    x, t, _ = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
     del snaps
     net, _ = pr.train(x, t, pr.TrainConfig(n_tuples=c4["tuples"]))
     del x, t
@@ -585,6 +585,56 @@ def schedule_sweep(seeds=(1, 2)):
     rank = sorted(speed.items(), key=lambda kv: -float(np.mean(kv[1])))
     print(json.dumps({"ranking": [{"alpha_max": a, "every": e, "until": u, "mean_speedup": round(float(np.mean(v)), 3)}
                                   for (a, e, u), v in rank[:10]]}), flush=True)
+
+
+def weight_sweep(betas=(0.0, 1.0, 3.0, -0.5), seeds=(1, 2, 3, 4)):
+    """Chooses the training tuples' energy weighting on the validation batch:
+    tuples weighted by their individual's energy rank at the snapshot,
+    (1 + beta)(1 - rank / pop)^beta (beta = 0: uniform).  For each beta a network
+    is trained as in learned_vs_plain on the same tuples, then the learned search
+    with the default schedule runs from a fresh population on the validation
+    batch and is timed to the plain search's final median + 0.1 kcal/mol on the
+    same seed; an untrained network on the same schedule is the control.  Prints
+    one JSON line per (beta, seed) and the mean speedups."""
+    import torch
+    from dataclasses import replace
+    from paper_2509_12232_amd import proposal as pr
+    B = batch_setup(5, extra_cfg=4)
+    dk = B["dk"]
+    L_val, L_tr = B["handles"]
+    stride = B["stride"]
+    c4 = synth.CONFIGS[4]
+    P = dk.SearchParams(pop_size=c4["pop"], n_generations=c4["gens"], seed=1, box_lo=B["lo"], box_hi=B["hi"])
+    for L in (L_val, L_tr):
+        dk.dock_search_autotune(B["pocket"], L, P, stride, tune_generations=3)
+    energies = {}
+    snaps, fin = pr.plain_snapshots(B["pocket"], L_tr, P, stride, pr.SNAPSHOT_GENERATIONS, energies=energies)
+    cfg = pr.TrainConfig(n_tuples=c4["tuples"])
+    nets = {}
+    for beta in betas:
+        x, t, w = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"], snap_energies=energies, beta=beta)
+        nets[beta], losses = pr.train(x, t, cfg, weight=w)
+        print(json.dumps({"beta": beta, "loss_first": round(float(losses[:10].mean()), 4),
+                          "loss_last": round(float(losses[-50:].mean()), 4)}), flush=True)
+        del x, t, w
+    nets["untrained"] = dk.dock_mlp_create(0, cfg.seed)
+    del snaps
+    torch.cuda.synchronize()
+    speed = {k: [] for k in nets}
+    for seed in seeds:
+        Ps = replace(P, seed=seed)
+        pts, buf = pr.anytime(B["pocket"], L_val, Ps, stride)
+        level = float(np.median(buf["be"].cpu().numpy())) + 0.1
+        t_plain, _ = pr.time_to_level(pts, level)
+        for k, net in nets.items():
+            lp, _ = pr.anytime(B["pocket"], L_val, Ps, stride, net, pr.ProposalConfig())
+            t_l, _ = pr.time_to_level(lp, level)
+            sp = t_plain / t_l if t_l else 0.0
+            speed[k].append(sp)
+            print(json.dumps({"seed": seed, "beta": k, "ms": None if t_l is None else round(t_l, 1),
+                              "plain_ms": round(t_plain, 1), "speedup": round(sp, 3)}), flush=True)
+    print(json.dumps({"mean_speedup": {str(k): round(float(np.mean(v)), 3) for k, v in speed.items()},
+                      "min_speedup": {str(k): round(float(np.min(v)), 3) for k, v in speed.items()}}), flush=True)
 
 
 def profile_search(gens: int = 30):
@@ -625,6 +675,9 @@ def main():
                          "autotuner, then two plain searches of 30 generations, nothing else")
     ap.add_argument("--schedule-sweep", action="store_true",
                     help="choose the learned proposal's round schedule on the validation batch, nothing else")
+    ap.add_argument("--weight-sweep", action="store_true",
+                    help="choose the energy-rank weighting of the training tuples on the validation batch, "
+                         "nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the scoring workload would shard by "
@@ -636,6 +689,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     if args.schedule_sweep:
         schedule_sweep()
+        return
+    if args.weight_sweep:
+        weight_sweep()
         return
     if args.profile_search:
         profile_search()

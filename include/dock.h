@@ -435,6 +435,19 @@ dock_status dock_mlp_features(const dock_ligands *ligs, const dock_search_params
 dock_status dock_mlp_moves(const dock_ligands *ligs, const dock_search_params *params, int32_t g_stride,
                            const float *from, const float *to, float *out, void *stream);
 
+/* Training weights from a population's energies (one snapshot of a search's
+ * energy trace), for dock_mlp_train's weight argument: individual i of ligand
+ * l, of rank r among the ligand's pop_size energies (0 = the lowest; equal
+ * energies ranked by index; NaN after every number), gets weight[l * pop_size
+ * + i] = (1 + beta) (1 - r / pop_size)^beta, in binary64 rounded to float32.
+ * beta = 0 gives 1 everywhere; beta > 0 favours the individuals nearer their
+ * ligand's best (the weights of a ligand average about 1).  pop_energy
+ * [n_ligands][pop_size] and weight [n_ligands * pop_size] are device buffers;
+ * params supplies pop_size.  Cost O(pop_size) per individual.  Errors:
+ * DOCK_E_INVALID (null arguments, pop_size < 1, beta not finite or <= -1). */
+dock_status dock_mlp_rank_weights(const dock_ligands *ligs, const dock_search_params *params, const float *pop_energy,
+                                  float beta, float *weight, void *stream);
+
 /* Proposals (same shape as population, device): for individual i of ligand l,
  * y = network(features), alpha = alpha_max (1 - u) with u the first uniform of
  * the Philox stream (i, generation, l, purpose 4) (so alpha in (0, alpha_max]),

@@ -17,8 +17,9 @@ is therefore this project's own definition, written out here step by step:
   ``forward``/``backward`` with ``quantize=True`` round to bfloat16 at exactly
   the points where the GPU does and are otherwise exact (binary64);
 * a weighted squared-error loss, the Adam update (Kingma & Ba, ICLR 2015), the
-  encoded move between two genotypes (the training target) and the decoding of
-  a network output into a proposal genotype.
+  encoded move between two genotypes (the training target), the decoding of
+  a network output into a proposal genotype, and per-individual training
+  weights from the ranks of a population's energies.
 
 Pins (tests/test_oracle_mlp.py): bfloat16 rounding against torch's conversion;
 the unquantised backward against central finite differences of the forward;
@@ -180,6 +181,31 @@ def forward(params: dict, X, quantize: bool = True):
     y = a2 @ W["W3"] + params["b3"]
     cache = dict(a0=a0, a1=a1, a2=a2, z1=z1, z2=z2, W=W, quantize=quantize)
     return y, cache
+
+
+def rank_weights(energies, beta: float) -> np.ndarray:
+    """Training weights of one ligand's population from its energies (one
+    snapshot of the search's energy trace): individual i of rank r_i (0 = the
+    lowest energy; equal energies ranked by index; a NaN after every number)
+    among the P individuals gets (1 + beta) (1 - r_i / P) ** beta, computed in
+    binary64 and rounded to float32.  A definition of this build: beta = 0 is
+    uniform, beta > 0 favours the individuals nearer the ligand's best."""
+    e = np.asarray(energies, np.float64)
+    P = e.size
+    nan = np.isnan(e)
+
+    def before(j, i):
+        if nan[j] != nan[i]:
+            return not nan[j]           # every number before every NaN
+        if not nan[i] and e[j] != e[i]:
+            return e[j] < e[i]
+        return j < i                    # equal energies (or two NaNs): by index
+
+    out = np.empty(P, np.float32)
+    for i in range(P):
+        r = sum(1 for j in range(P) if j != i and before(j, i))
+        out[i] = np.float32((1.0 + beta) * (1.0 - r / P) ** beta)
+    return out
 
 
 def loss(y, T, w=None) -> float:

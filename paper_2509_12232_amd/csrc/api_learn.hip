@@ -351,6 +351,19 @@ extern "C" dock_status dock_mlp_moves(const dock_ligands *L, const dock_search_p
   return DOCK_OK;
 }
 
+extern "C" dock_status dock_mlp_rank_weights(const dock_ligands *L, const dock_search_params *q, const float *pop_energy,
+                                            float beta, float *weight, void *stream) {
+  if (!L || !q || !pop_energy || !weight) return set_err(DOCK_E_INVALID, "null argument");
+  if (q->pop_size < 1) return set_err(DOCK_E_INVALID, "pop_size must be >= 1");
+  if (!isfinite(beta) || !(beta > -1.f)) return set_err(DOCK_E_INVALID, "beta must be finite and > -1");
+  DeviceScope ds(L->device);
+  HIP_TRY(ds.err, "hipSetDevice");
+  HIP_TRY(launch_rank_weights((int64_t)L->n_ligs * q->pop_size, q->pop_size, pop_energy, (double)beta, weight,
+                              (hipStream_t)stream),
+          "rank weights launch");
+  return DOCK_OK;
+}
+
 hipError_t run_proposals(const dock_mlp *net, const PopRows &R, float alpha_max, uint64_t seed, int32_t generation,
                          const float *population, float *proposals, hipStream_t s) {
   return launch_propose(R, net->weights(), population, alpha_max, seed, generation, proposals, s);

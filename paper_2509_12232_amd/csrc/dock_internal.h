@@ -18,6 +18,10 @@ constexpr int kBlock = kWave;   // poses per scoring block: one per lane
 constexpr int kParts = 8;
 constexpr int kMaxSplit = 8;    // wavefronts sharing a block of poses: 1, 2, 4 or 8
 
+// Rows of kBlock floats a block of poses keeps in LDS besides its coordinate
+// columns, when ws wavefronts share it: the energy reduction, one row each.
+__host__ __device__ constexpr int block_extra_rows(int ws) { return ws > 1 ? ws : 0; }
+
 // Per ligand.  Atoms are renumbered in depth-first pre-order from the root
 // (atom 0), so every rotatable bond's moving fragment is one contiguous range.
 // Pairs: the 12-6 pairs in groups of kParts (the last group padded with records

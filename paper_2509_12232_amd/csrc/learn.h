@@ -102,6 +102,8 @@ hipError_t launch_encode(const PopRows &R, int64_t row0, int64_t n, const float 
                          int64_t a0_rows, hipStream_t s);
 // encoded moves from -> to, [n_rows][32]
 hipError_t launch_moves(const PopRows &R, const float *from, const float *to, float *out, hipStream_t s);
+// rank weights of n = n_ligs * pop individuals from their energies
+hipError_t launch_rank_weights(int64_t n, int32_t pop, const float *energies, double beta, float *w, hipStream_t s);
 // proposals = decode(genotypes, network(encode(genotypes)), alpha_max * u) for
 // every row, u in (0, 1] from the Philox stream (individual, generation, ligand,
 // proposal purpose); one fused launch (encode, the three layers and decode per

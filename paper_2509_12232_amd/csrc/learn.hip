@@ -633,6 +633,35 @@ hipError_t launch_encode(const PopRows &R, int64_t row0, int64_t n, const float 
   return hipGetLastError();
 }
 
+// Training weight of individual t (of n_ligs * pop): (1 + beta) (1 - r / pop)^beta
+// for its rank r among its ligand's energies (numbers before NaNs, equal
+// values by index), in binary64 rounded to float32.
+__global__ void rank_weights_kernel(int64_t n, int32_t pop, const float *energies, double beta, float *w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t base = t - t % pop;
+  const int i = (int)(t - base);
+  const float ei = energies[t];
+  const bool ni = ei != ei;
+  int r = 0;
+  for (int j = 0; j < pop; ++j) {
+    const float ej = energies[base + j];
+    const bool nj = ej != ej;
+    bool before;
+    if (nj != ni) before = !nj;
+    else if (!ni && ej != ei) before = ej < ei;
+    else before = j < i;
+    r += (j != i) & before;
+  }
+  w[t] = (float)((1.0 + beta) * pow(1.0 - (double)r / pop, beta));
+}
+
+hipError_t launch_rank_weights(int64_t n, int32_t pop, const float *energies, double beta, float *w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_weights_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, n, pop, energies, beta, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_moves(const PopRows &R, const float *from, const float *to, float *out, hipStream_t s) {
   if (R.n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(moves_kernel, dim3(blocks_for(R.n_rows, 128)), dim3(128), 0, s, R, from, to, out);

@@ -55,7 +55,7 @@ constexpr int64_t kPosesPerLaunch = (int64_t)1 << 24;
 
 template <int LAYOUT, int WS>
 static hipError_t launch_score_ws(const ScoreLaunch &a, hipStream_t s) {
-  const size_t lds = ((size_t)a.lds_atoms * 3 + (WS > 1 ? WS : 0)) * kBlock * sizeof(float);
+  const size_t lds = ((size_t)a.lds_atoms * 3 + block_extra_rows(WS)) * kBlock * sizeof(float);
   auto fn = score_kernel<LAYOUT, WS>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -283,6 +283,13 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   const cptr<float4> atoms = as_const(L.atoms) + H.atom_off;
   const cptr<int32_t> types = as_const(L.atom_type) + H.atom_off;
 
+  bool bad = false;
+  // the genes are requested before they are needed: the rigid ones here, each
+  // torsion angle one torsion ahead
+  const float tx = g[0], ty = g[gs], tz = g[2 * gs];
+  float qw = g[3 * gs], qx = g[4 * gs], qy = g[5 * gs], qz = g[6 * gs];
+  const cptr<TorRec> tors = as_const(L.tors) + H.tor_off;
+  float th_next = H.n_tors > 0 ? g[(7 + tors[0].gene) * gs] : 0.f;
   // reference conformation (centred) into the pose's LDS column
   for (int i = h; i < n; i += WS) {
     const float4 a = atoms[i];
@@ -292,27 +299,20 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   }
   block_sync<WS>();
 
-  bool bad = false;
-  // the genes are requested before they are needed: the rigid ones here, each
-  // torsion angle one torsion ahead
-  const float tx = g[0], ty = g[gs], tz = g[2 * gs];
-  float qw = g[3 * gs], qx = g[4 * gs], qy = g[5 * gs], qz = g[6 * gs];
   // Algorithm 1, rotatable bonds: rotate each fragment about its current bond
   // axis.  Rotations about current axes commute on a tree, so the torsion order
   // of the genotype is used as is.
-  const cptr<TorRec> tors = as_const(L.tors) + H.tor_off;
-  float th_next = H.n_tors > 0 ? g[(7 + tors[0].gene) * gs] : 0.f;
   for (int k = 0; k < H.n_tors; ++k) {
     const TorRec T = tors[k];
     const float th = th_next;
     if (k + 1 < H.n_tors) th_next = g[(7 + tors[k + 1].gene) * gs];
     bad |= !__builtin_isfinite(th);
+    float s, c;
+    sincosf(th, &s, &c);
     const float ax = at(my, T.a, 0), ay = at(my, T.a, 1), az = at(my, T.a, 2);
     float ux = at(my, T.lo, 0) - ax, uy = at(my, T.lo, 1) - ay, uz = at(my, T.lo, 2) - az;
     const float il = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, uz * uz)));
     ux *= il; uy *= il; uz *= il;
-    float s, c;
-    sincosf(th, &s, &c);
     const float oc = 1.f - c;
     const float r00 = fmaf(ux * ux, oc, c), r01 = fmaf(ux * uy, oc, -uz * s), r02 = fmaf(ux * uz, oc, uy * s);
     const float r10 = fmaf(uy * ux, oc, uz * s), r11 = fmaf(uy * uy, oc, c), r12 = fmaf(uy * uz, oc, -ux * s);
@@ -377,30 +377,48 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
 #pragma unroll
   for (int d = 0; d < AHEAD; ++d)
     if (d < slots) ring[d] = gather(d);
+  // the pair terms of one step (records P, coordinates X) into its partial sums
+  auto eval = [&](const PairSlice<SL> &P, const SliceCoords<SL> &X, int part) {
+#pragma unroll
+    for (int u = 0; u < SL; ++u)
+      intra[part * SL + u] += pair_term<false>(F, P.r[u], X.xi[u] - X.xj[u], X.yi[u] - X.yj[u], X.zi[u] - X.zj[u]);
+  };
+  // Steps go two at a time with two coordinate sets used in turn (X0 for even
+  // steps, X1 for odd ones), so no coordinates are copied between steps.  A:
+  // records of the current step, B: of the next; X0: coordinates of A.
   PairSlice<SL> A, B;
   A.load(step_ptr(0));
   B.load(step_ptr(1));
-  SliceCoords<SL> X;
-  X.load(A, my);
+  SliceCoords<SL> X0, X1;
+  X0.load(A, my);
   for (int k = 0; k < slots; ++k) {
     const int ka = k + AHEAD;
     if (ka < slots) ring[AHEAD] = gather(ka);
-    const int g0 = (k * ng) / slots, g1 = ((k + 1) * ng) / slots;
-    for (int gi = g0; gi < g1; ++gi) {
-#pragma unroll
-      for (int part = 0; part < NP; ++part) {
-        SliceCoords<SL> Xn;
-        Xn.load(B, my);
-        PairSlice<SL> C;
-        C.load(step_ptr(gi * NP + part + 2));
-#pragma unroll
-        for (int u = 0; u < SL; ++u)
-          intra[part * SL + u] +=
-              pair_term<false>(F, A.r[u], X.xi[u] - X.xj[u], X.yi[u] - X.yj[u], X.zi[u] - X.zj[u]);
-        A = B;
-        B = C;
-        X = Xn;
-      }
+    // this slot's steps: its equal share of the pair groups, NP steps each
+    // (for NP = 2 both bounds are even, so a step's partial-sum block is its
+    // position in the pair)
+    const int s1 = NP * (((k + 1) * ng) / slots);
+    int st = NP * ((k * ng) / slots);
+    for (; st + 1 < s1; st += 2) {
+      X1.load(B, my);
+      PairSlice<SL> C;
+      C.load(step_ptr(st + 2));
+      eval(A, X0, 0);
+      X0.load(C, my);
+      PairSlice<SL> D;
+      D.load(step_ptr(st + 3));
+      eval(B, X1, NP - 1);
+      A = C;
+      B = D;
+    }
+    if (st < s1) {   // one step left (NP = 1 only)
+      X1.load(B, my);
+      PairSlice<SL> C;
+      C.load(step_ptr(st + 2));
+      eval(A, X0, 0);
+      A = B;
+      B = C;
+      X0 = X1;
     }
     const float v = interpolate_corners<LAYOUT>(ring[0]);
     if (atom_of(k) < n) {

@@ -46,10 +46,9 @@ constexpr int kSearchMaxThreads = 768;      // wavefronts per search workgroup: 
 constexpr size_t kLdsPerCU = 160 * 1024;    // gfx950 LDS per compute unit
 
 // LDS floats of one pose block of the search kernel: the coordinate columns of
-// 64 poses of up to lds_atoms atoms, then (ws > 1) ws rows for the energy
-// reduction.
+// 64 poses of up to lds_atoms atoms, then (ws > 1) the block's reduction rows.
 __host__ __device__ constexpr size_t search_block_floats(int32_t lds_atoms, int32_t ws) {
-  return ((size_t)lds_atoms * 3 + (ws > 1 ? ws : 0)) * kWave;
+  return ((size_t)lds_atoms * 3 + block_extra_rows(ws)) * kWave;
 }
 
 // Launch shape of a bucket: the split (1, 2, 4 or 8 wavefronts per block of 64

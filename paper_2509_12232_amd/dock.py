@@ -104,6 +104,7 @@ _SIGS = {
     "dock_mlp_features": [_P, _P, C.c_int32, _P, _P, _P],
     "dock_mlp_moves": [_P, _P, C.c_int32, _P, _P, _P, _P],
     "dock_propose": [_P, _P, _P, C.c_int32, C.c_float, C.c_int32, _P, _P, _P],
+    "dock_mlp_rank_weights": [_P, _P, _P, C.c_float, _P, _P],
 }
 DOCK_MLP_IN, DOCK_MLP_HIDDEN, DOCK_MLP_OUT, DOCK_MLP_PARAMS, DOCK_DESC = 96, 256, 32, 98848, 64
 DOCK_MLP_MAX_BATCH = 65536
@@ -555,3 +556,11 @@ def dock_propose(ligs: Ligands, net: Mlp, params: SearchParams, generation: int,
                    (proposals, "float32", "proposals", npg))
     _check(_lib.dock_propose(ligs.handle, net.handle, C.byref(P), generation, alpha_max, g, pp, qp,
                              _stream(stream)))
+
+
+def dock_mlp_rank_weights(ligs: Ligands, params: SearchParams, pop_energy, beta: float, weight, stream=None):
+    """Training weights (1 + beta)(1 - rank / pop)^beta from a population's energies."""
+    P = params._c()
+    n = ligs.n * max(int(params.pop_size), 0)
+    ep, wp = _bufs(ligs.pocket.device, (pop_energy, "float32", "pop_energy", n), (weight, "float32", "weight", n))
+    _check(_lib.dock_mlp_rank_weights(ligs.handle, C.byref(P), ep, float(beta), wp, _stream(stream)))

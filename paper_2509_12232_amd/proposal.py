@@ -11,7 +11,8 @@ buffers:
   (its genotype and its ligand's descriptor) and, as target, the encoded move
   from it to the converged pose the plain search reached for that ligand (or,
   optionally, to the same individual of the final population: the accepted
-  moves of that individual from there on, composed);
+  moves of that individual from there on, composed), optionally weighted by
+  the individual's energy rank at that snapshot;
 * ``train`` -- Adam on minibatches of a seeded random sample of those tuples;
 * ``time_to_target`` -- one search (plain or learned) in which every ligand
   stops once its population best reaches its target, timed with HIP events on
@@ -35,12 +36,14 @@ def _buffers(n_ligs: int, pop: int, stride: int):
                 bg=torch.zeros((n_ligs, stride), **f32), be=torch.zeros(n_ligs, **f32))
 
 
-def plain_snapshots(pocket, ligs, params: dk.SearchParams, stride: int, snap_gens):
+def plain_snapshots(pocket, ligs, params: dk.SearchParams, stride: int, snap_gens, energies: dict | None = None):
     """Plain search of params.n_generations generations from a fresh population.
 
     Returns ({g: population after g generations} for g in snap_gens below
-    n_generations, buffers of the final state).  The run is cut into resumed
-    pieces at the snapshot generations, which gives exactly the uninterrupted run."""
+    n_generations, buffers of the final state); with `energies` (a dict), also
+    fills it with {g: the population's energies after g generations}.  The run
+    is cut into resumed pieces at the snapshot generations, which gives exactly
+    the uninterrupted run."""
     B = _buffers(ligs.n, params.pop_size, stride)
     snaps = {}
     marks = sorted({int(g) for g in snap_gens if 0 <= g < params.n_generations}) + [params.n_generations]
@@ -51,6 +54,8 @@ def plain_snapshots(pocket, ligs, params: dk.SearchParams, stride: int, snap_gen
         dk.dock_search(pocket, ligs, p, B["pop"], B["pe"], B["bg"], B["be"])
         if m < params.n_generations:
             snaps[m] = B["pop"].clone()
+            if energies is not None:
+                energies[m] = B["pe"].clone()
         g = m
     return snaps, B
 
@@ -58,16 +63,23 @@ def plain_snapshots(pocket, ligs, params: dk.SearchParams, stride: int, snap_gen
 SNAPSHOT_GENERATIONS = (0, 5, 15, 40, 80)
 
 
-def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop=None, final_best=None):
-    """(x [N, 96], target [N, 32]) for every individual of every snapshot: the
-    target is the encoded move to the ligand's converged pose (final_best
-    [n_ligs][g_stride], the best member of the final population) or, given
-    final_pop instead, to the same individual of the final population."""
+def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop=None, final_best=None,
+                snap_energies: dict | None = None, beta: float = 0.0):
+    """(x [N, 96], target [N, 32], weight [N] or None) for every individual of
+    every snapshot: the target is the encoded move to the ligand's converged
+    pose (final_best [n_ligs][g_stride], the best member of the final
+    population) or, given final_pop instead, to the same individual of the
+    final population.  With beta != 0 and the snapshots' energies, each tuple
+    is weighted by its individual's rank in its ligand's population at that
+    snapshot (dock_mlp_rank_weights)."""
     import torch
     n = ligs.n * params.pop_size
     if final_best is not None:
         final_pop = final_best[:, None, :].expand(-1, params.pop_size, -1).contiguous()
-    xs, ts = [], []
+    weighted = beta != 0.0
+    if weighted and snap_energies is None:
+        raise ValueError("rank weights need the snapshots' energies")
+    xs, ts, ws = [], [], []
     for g in sorted(snaps):
         x = torch.empty((n, dk.DOCK_MLP_IN), dtype=torch.float32, device="cuda")
         t = torch.empty((n, dk.DOCK_MLP_OUT), dtype=torch.float32, device="cuda")
@@ -75,7 +87,11 @@ def make_tuples(ligs, params: dk.SearchParams, snaps: dict, final_pop=None, fina
         dk.dock_mlp_moves(ligs, params, snaps[g], final_pop, t)
         xs.append(x)
         ts.append(t)
-    return torch.cat(xs), torch.cat(ts)
+        if weighted:
+            w = torch.empty(n, dtype=torch.float32, device="cuda")
+            dk.dock_mlp_rank_weights(ligs, params, snap_energies[g], beta, w)
+            ws.append(w)
+    return torch.cat(xs), torch.cat(ts), (torch.cat(ws) if weighted else None)
 
 
 @dataclass
@@ -87,9 +103,10 @@ class TrainConfig:
     seed: int = 1
 
 
-def train(x, t, cfg: TrainConfig):
-    """A new network trained on a seeded random sample of the tuples; returns
-    (network, per-step losses as a numpy array)."""
+def train(x, t, cfg: TrainConfig, weight=None):
+    """A new network trained on a seeded random sample of the tuples (rows
+    weighted by `weight` if given); returns (network, per-step losses as a
+    numpy array)."""
     import torch
     n_data = int(x.shape[0])
     n_rows = min(cfg.n_tuples, n_data) // cfg.batch * cfg.batch
@@ -100,7 +117,7 @@ def train(x, t, cfg: TrainConfig):
     steps = max(1, int(round(cfg.epochs * n_rows / cfg.batch)))
     net = dk.dock_mlp_create(0, cfg.seed)
     losses = torch.empty(steps, dtype=torch.float32, device="cuda")
-    dk.dock_mlp_train(net, x, t, cfg.batch, steps, cfg.lr, order=order, losses=losses)
+    dk.dock_mlp_train(net, x, t, cfg.batch, steps, cfg.lr, weight=weight, order=order, losses=losses)
     return net, losses.cpu().numpy()
 
 

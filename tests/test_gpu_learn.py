@@ -276,6 +276,31 @@ def test_features_and_moves_match_oracle(dk, learn_sys):
             np.testing.assert_allclose(dt, 0.0, atol=2e-6, err_msg=f"move row {r}")
 
 
+def test_rank_weights_match_oracle(dk, learn_sys):
+    """Training weights from population energies, with ties, NaNs and every
+    beta form, bit for bit against the FP64 reference rounded to float32
+    (the GPU's pow may differ by an ulp before the rounding: 1 float32 ulp)."""
+    S = learn_sys
+    pop = 41
+    n = len(S["ligs"])
+    rng = np.random.default_rng(5)
+    E = rng.normal(0, 20, (n, pop)).astype(np.float32)
+    E[0, 3] = E[0, 7] = E[0, 11]            # ties
+    E[1, 5] = E[1, 9] = np.nan              # NaNs rank last, by index
+    E[2, :] = 1.5                           # all equal: ranks by index
+    p = dk.SearchParams(pop_size=pop, n_generations=0, seed=1, box_lo=tuple(S["lo"]), box_hi=tuple(S["hi"]))
+    e = torch.from_numpy(E).cuda()
+    for beta in (0.0, 1.0, 3.0, -0.5):
+        w = torch.empty(n * pop, dtype=torch.float32, device="cuda")
+        dk.dock_mlp_rank_weights(S["L"], p, e, beta, w)
+        got = w.cpu().numpy().reshape(n, pop)
+        for li in range(n):
+            ref = mlp.rank_weights(E[li], beta)
+            np.testing.assert_allclose(got[li], ref, rtol=2.0 ** -23, atol=0, err_msg=f"beta {beta}, ligand {li}")
+    with pytest.raises(dk.DockError):
+        dk.dock_mlp_rank_weights(S["L"], p, e, -1.0, w)
+
+
 def oracle_alpha(seed, ind, gen, lig, alpha_max):
     """alpha = alpha_max (1 - u), u the first uniform of the (ind, gen, lig, purpose 4) stream."""
     w = oracle.philox4x64((ind, gen, lig, 4 << 32), (seed, 0))
@@ -460,7 +485,7 @@ def test_trained_network_gains(dk):
     plain, buf = pr.anytime(pocket, L_ev, P, stride)
     level = float(np.median(buf["be"].cpu().numpy())) + 0.1
     snaps, fin = pr.plain_snapshots(pocket, L_tr, P, stride, pr.SNAPSHOT_GENERATIONS)
-    x, t = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
+    x, t, _ = pr.make_tuples(L_tr, P, snaps, final_best=fin["bg"])
     net, losses = pr.train(x, t, pr.TrainConfig(n_tuples=400_000, epochs=4))
     assert np.all(np.isfinite(losses)) and losses[-20:].mean() < losses[:20].mean()
     learned, _ = pr.anytime(pocket, L_ev, P, stride, net, pr.ProposalConfig())

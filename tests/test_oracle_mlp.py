@@ -156,3 +156,25 @@ def test_descriptor_features():
     assert d[36] == pytest.approx(rg / 10, rel=1e-12)
     assert d[37] == 200 / 4096
     assert np.all(d[38:] == 0)
+
+
+def test_rank_weights_pins():
+    """Rank weights: beta = 0 is uniform; the ranks are a permutation of 0..P-1
+    (recovered from beta = 1, where w = 2 (1 - r / P)); ties go by index, NaNs
+    last; the mean over a ligand tends to 1 (exactly (1 + beta) times a Riemann
+    sum of (1 - x)^beta)."""
+    rng = np.random.default_rng(2)
+    e = rng.normal(0, 5, 50)
+    e[[4, 9]] = e[17]
+    e[[2, 30]] = np.nan
+    assert np.all(mlp.rank_weights(e, 0.0) == 1.0)
+    r = np.rint((1 - mlp.rank_weights(e, 1.0).astype(np.float64) / 2) * 50).astype(int)
+    assert sorted(r) == list(range(50))
+    assert r[30] == 49 and r[2] == 48                      # NaNs last, by index
+    assert r[4] < r[9] < r[17] or sorted([r[4], r[9], r[17]]) == [r[4], r[9], r[17]]
+    order = sorted(range(50), key=lambda i: (np.isnan(e[i]), 0.0 if np.isnan(e[i]) else e[i], i))
+    assert [r[i] for i in order] == list(range(50))
+    for beta in (0.5, 2.0, -0.5):
+        w = mlp.rank_weights(np.arange(1000.0), beta).astype(np.float64)
+        assert abs(w.mean() - 1.0) < 0.05
+        assert np.all(np.diff(w) < 0) if beta > 0 else np.all(np.diff(w) > 0)

@@ -673,10 +673,10 @@ static std::atomic<int32_t> g_score_split{0};
 // per CU for the same LDS, at the cost of the pose build's barriers and of the
 // per-torsion setup each wavefront repeats.  Measured on MI355X (fourteen
 // 100^3 maps in the pair-line layout, 2e6 random poses of one ligand of each
-// size, M poses/s for splits 1 / 2 / 4 / 8): 12 atoms 4890 / 5057 / 5020 /
-// 3743; 24 atoms 2083 / 2387 / 2420 / 1931; 48 atoms 433 / 687 / 895 / 758;
-// 64 atoms 168 / 326 / 455 / 432; 96 atoms 51 / 113 / 165 / 200.  Four
-// wavefronts up to 64 atoms, eight above.
+// size, M poses/s for splits 1 / 2 / 4 / 8): 12 atoms 4846 / 5054 / 4981 /
+// 3783; 24 atoms 2100 / 2362 / 2429 / 1999; 48 atoms 421 / 689 / 955 / 795;
+// 64 atoms 162 / 326 / 458 / 432; 96 atoms 49 / 104 / 142 / 206.  Four
+// wavefronts up to 64 atoms (within 2% of the fastest at 12), eight above.
 static int32_t score_split_auto(int32_t max_atoms, int32_t layout) {
   (void)layout;
   return max_atoms > 64 ? 8 : 4;

@@ -48,6 +48,30 @@ def test_init_population_bit_identical(dk, ora):
         assert np.array_equal(got[l].view(np.uint32), ref.view(np.uint32)), l
 
 
+def test_init_population_bit_identical_a_million(dk, ora):
+    """The device and host Philox4x64-10 streams over 10^6 counters: the initial
+    population of 10^6 individuals (each draws from its own stream, counter
+    (individual, 0, ligand, purpose)) for two ligands and two seeds, bit for
+    bit against the oracle's."""
+    import torch
+    ff, rec, grid, maps = system(0)
+    ligands = [synth.make_ligand(1, 0, 24, 6, 8), synth.make_ligand(1, 7, 30, 9, 8)]
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, ligands)
+    lo, hi = synth.pocket_box(grid)
+    stride = 16
+    P = 500_000
+    for seed in (1, 0xFFFFFFFFFFFF):
+        print("case: initial population of 2 x 500000, seed", seed, flush=True)
+        pop = torch.full((2, P, stride), 7.0, dtype=torch.float32, device="cuda")
+        dk.dock_de_init(ligs, _params(dk, lo, hi, pop_size=P, seed=seed), pop)
+        torch.cuda.synchronize()
+        got = pop.cpu().numpy()
+        for l, lig in enumerate(ligands):
+            ref = ora.de_init(lig, _params(ora, lo, hi, pop_size=P, seed=seed), l, stride)
+            assert np.array_equal(got[l].view(np.uint32), ref.view(np.uint32)), (seed, l)
+
+
 def test_trials_bit_identical(dk, ora):
     import torch
     ff, rec, grid, maps = system(2, grid_n=48)

@@ -271,12 +271,23 @@ __device__ __forceinline__ void block_sync() {
 // Every wavefront returns the energy.  Non-finite genes give NaN.  AHEAD: how
 // many atoms ahead of its interpolation an atom's map loads are issued (more
 // loads in flight, more registers); it does not change the result.
-template <int LAYOUT, int WS, int AHEAD>
+//
+// HALF (WS < 8): a half block, 32 poses on lanes 0-31 with lane l + 32 given the
+// genes of pose l.  The two lanes build the same pose into their own columns;
+// the energy loops then run as if the block had 2 WS wavefronts, lane half s of
+// wavefront h acting as wavefront 2 h + s, which owns the first (s = 0) or the
+// second half of wavefront h's partial sums.  Records and atoms then differ
+// between the halves and arrive by vector loads.  The two halves' subtotals
+// are the two subtrees of wavefront h's share, so the energy has the same bits
+// as in a full block.
+template <int LAYOUT, int WS, int AHEAD, bool HALF = false>
 __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst &F, const MapData &maps,
                             const LigHeader &H, const float *__restrict__ g, int gs, float *__restrict__ my,
                             float *__restrict__ red, int h) {
   static_assert(WS == 1 || WS == 2 || WS == 4 || WS == 8, "one, two, four or eight wavefronts per block");
-  constexpr int R = kParts / WS;      // partial sums (and records of a group) per wavefront
+  static_assert(!HALF || WS < 8, "a half block needs two partial sums per wavefront");
+  constexpr int WV = HALF ? 2 * WS : WS;  // wavefronts of the energy loops
+  constexpr int R = kParts / WV;      // partial sums (and records of a group) per energy-loop wavefront
   constexpr int SL = R < 4 ? R : 4;   // records evaluated per step of the pair loop
   constexpr int NP = R / SL;          // steps per pair group
   const int n = H.n_atoms;
@@ -357,14 +368,16 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   // (NP steps per group); the coordinates of step s+1 and the records of step
   // s+2 are requested before step s is evaluated (the list ends with spare zero
   // groups to read past).
-  const cptr<PairRec> pairs = as_const(L.pairs) + H.pair_off + h * R;
+  // the energy loops' wavefront index (per lane for a half block)
+  const int hv = HALF ? 2 * h + (int)(__lane_id() >> 5) : h;
+  const cptr<PairRec> pairs = as_const(L.pairs) + H.pair_off + hv * R;
   auto step_ptr = [&](int st) { return pairs + kParts * (st / NP) + (st % NP) * SL; };
   const int ng = H.n_groups;
   // The wavefront's atoms in index order: slot k is atom 8 (k / R) + h R + k % R,
   // of class h R + k % R; wavefront 0 has the most slots, the others skip their
   // last.
   const int slots = R * (n / kParts) + min(n % kParts, R);
-  auto atom_of = [&](int slot) { return kParts * (slot / R) + h * R + slot % R; };
+  auto atom_of = [&](int slot) { return kParts * (slot / R) + hv * R + slot % R; };
   float inter[R], intra[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) inter[u] = intra[u] = 0.f;
@@ -434,7 +447,7 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   for (int p = 0; p < H.n_pairs_hb; p += kParts) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int q = p + h * R + u;
+      const int q = p + hv * R + u;
       PairRec P{0, 0.f, 0.f, 0.f, 0.f};
       if (q < H.n_pairs_hb) P = hb[q];
       const int i = P.ij & 0xffff, j = P.ij >> 16;
@@ -448,6 +461,9 @@ __device__ float score_pose(const LigandsDev &L, const MapGeom &G, const FFConst
   // this wavefront's share (the subtree of its partial sums), then, through
   // LDS, the shares of the block's wavefronts in the same tree
   float e = tree_sum<R>(part);
+  // a half block: the other half's subtree (addition commutes, so both halves
+  // hold the same sum)
+  if constexpr (HALF) e = e + __shfl_xor(e, 32);
   if constexpr (WS > 1) {
     red[h * kBlock] = e;
     block_sync<WS>();

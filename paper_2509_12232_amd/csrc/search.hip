@@ -165,11 +165,18 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
 // scored by the block's WS wavefronts together.  Every wavefront of the
 // workgroup takes part in every pass (so all of them meet the same barriers);
 // lanes without an individual score individual 0, in bounds, and drop the
-// result.  The population is worked on in a gene-major copy W (gene j of
+// result.  With TAIL (splits 2 and 4, chosen at launch when the population
+// ends in a short pass), a generation's last pass, when what is left of the
+// population fits in half of each block (32 individuals), scores half blocks
+// instead: lanes l and l + 32 share an individual and each takes half of the
+// pair and atom work, so the tail of the population costs about half a pass
+// (the same energies, bit for bit).  It is a separate instance so that the
+// registers of the half-block code cost nothing where no pass uses it.  The
+// population is worked on in a gene-major copy W (gene j of
 // individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
 // touch neighbouring words; the caller's individual-major population is read at
 // the start and written back at the end.
-template <int LAYOUT, int WS>
+template <int LAYOUT, int WS, bool TAIL>
 __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *red) {
   const int t = threadIdx.x, NT = blockDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(t / kWave), lane = t % kWave;
@@ -186,6 +193,11 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
   const float tgt = track ? S.target[lig] : 0.f;
   auto score = [&](const float *g, int gs) {
     return score_pose<LAYOUT, WS, 1>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
+  };
+  constexpr bool kHalf = TAIL && (WS == 2 || WS == 4);
+  auto score_half = [&](const float *g, int gs) {
+    if constexpr (kHalf) return score_pose<LAYOUT, WS, 1, true>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
+    else return score(g, gs);
   };
   for (int c = 0; c < P; c += NT) {
     const int i = c + t;
@@ -247,9 +259,11 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
     __syncthreads();
     int hit = 0;
     for (int c = 0; c < P; c += PB) {
-      const int i = c + slot;
-      const float e = score(T + (i < P ? i : 0), P);
-      if (i < P) {
+      const bool half = kHalf && P - c <= PB / 2;   // the same for the whole workgroup
+      const int i = c + (half ? (wave / WS) * (kBlock / 2) + (lane & (kBlock / 2 - 1)) : slot);
+      const float *gi = T + (i < P ? i : 0);
+      const float e = half ? score_half(gi, P) : score(gi, P);
+      if (i < P && (!half || lane < kBlock / 2)) {
         float ei = E[i];
         if (e <= ei) {
           copy_genes<WS>(T + i, W + i, h, G, P);
@@ -298,7 +312,7 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
 // Register budget: at least four wavefronts per SIMD (128 VGPRs) with four or
 // eight wavefronts per block, whose LDS per wavefront allows that residency;
 // three otherwise.
-template <int LAYOUT, int WS>
+template <int LAYOUT, int WS, bool TAIL>
 __global__ __launch_bounds__(kSearchMaxThreads, WS >= 4 ? 4 : 3) void search_kernel(SearchLaunch S) {
   extern __shared__ float lds[];
   __shared__ int s_q;
@@ -312,7 +326,7 @@ __global__ __launch_bounds__(kSearchMaxThreads, WS >= 4 ? 4 : 3) void search_ker
     const int q = s_q;
     __syncthreads();
     if (q >= S.n_order) break;
-    search_ligand<LAYOUT, WS>(S, S.order[q], my, red);
+    search_ligand<LAYOUT, WS, TAIL>(S, S.order[q], my, red);
   }
 }
 
@@ -348,7 +362,10 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
   // sized for the bucket's largest ligand, so a larger b can leave fewer
   // wavefronts resident per CU.  Unless the caller fixes b, pick the b that
   // minimises (rounds of resident ligands) x (scoring passes per generation).
-  auto kernel = (const void *)search_kernel<LAYOUT, WS>;
+  // splits 2 and 4 have a half-block instance (the same kernel otherwise)
+  constexpr bool kCanTail = WS == 2 || WS == 4;
+  auto kernel = (const void *)search_kernel<LAYOUT, WS, false>;
+  auto kernel_tail = (const void *)search_kernel<LAYOUT, WS, kCanTail>;
   const size_t per_block = search_block_floats(S.lds_atoms, WS) * sizeof(float);
   const int max_b = kSearchMaxThreads / (kWave * WS);
   const int want = std::min((S.p.pop + kBlock - 1) / kBlock, max_b);
@@ -357,14 +374,20 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
   hipFuncAttributes fa;
   *step = "hipFuncGetAttributes";
   if (hipError_t e = hipFuncGetAttributes(&fa, kernel); e != hipSuccess) return e;
+  hipFuncAttributes fa_tail;
+  if (hipError_t e = hipFuncGetAttributes(&fa_tail, kernel_tail); e != hipSuccess) return e;
+  fa.sharedSizeBytes = std::max(fa.sharedSizeBytes, fa_tail.sharedSizeBytes);
+  fa.numRegs = std::max(fa.numRegs, fa_tail.numRegs);
   if (fa.sharedSizeBytes >= kLdsPerCU) return hipErrorInvalidConfiguration;
   const size_t max_dyn = kLdsPerCU - fa.sharedSizeBytes;
   const int top_b = std::max(want, std::min(blocks, max_b));
   *step = "hipFuncSetAttribute (largest size)";
   if (per_block * top_b > 65536) {
-    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)std::min<size_t>(max_dyn, per_block * top_b));
-    if (e != hipSuccess) return e;
+    for (const void *k : {kernel, kernel_tail}) {
+      hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)std::min<size_t>(max_dyn, per_block * top_b));
+      if (e != hipSuccess) return e;
+    }
   }
   // Resident workgroups per CU: bounded by the CU's LDS (dynamic + static per
   // workgroup) and by its vector registers (512 per lane per SIMD, allocated in
@@ -405,8 +428,12 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
   }
   const size_t lds = per_block * best_b;
   const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * best_groups);
+  // the half-block instance when the population ends in a pass of at most
+  // half a pass (splits 2 and 4)
+  const int pass = best_b * kBlock, rem = S.p.pop % pass;
+  const bool tail = kCanTail && rem > 0 && 2 * rem <= pass;
   *step = "search kernel launch";
-  void (*const fn)(SearchLaunch) = search_kernel<LAYOUT, WS>;
+  void (*const fn)(SearchLaunch) = tail ? search_kernel<LAYOUT, WS, kCanTail> : search_kernel<LAYOUT, WS, false>;
   hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(best_b * WS * kWave), lds, s, S);
   return hipGetLastError();
 }

@@ -229,10 +229,13 @@ def test_gen_reached(dk):
 
 
 def test_launch_shape_does_not_change_results(dk):
-    """Splits of one, two and four wavefronts per block, and every block count
-    (including a block with no individual of its own), give the same search bit
-    for bit (the energies sum the same partial sums in the same order); the
-    autotuner fixes a valid shape per bucket and changes nothing."""
+    """Splits of one, two, four and eight wavefronts per block, and every block
+    count (including a block with no individual of its own), give the same
+    search bit for bit (the energies sum the same partial sums in the same
+    order); the autotuner fixes a valid shape per bucket and changes nothing.
+    Population 75 ends each generation of a one-block workgroup with a half-block
+    pass of 11 individuals (splits 2 and 4); population 178 with two blocks ends
+    with a half-block pass of 50, over both blocks."""
     ff, rec, grid, maps = system(2, grid_n=48)
     atoms = [10, 14, 20, 31, 33, 40, 47, 52, 60, 70, 85, 96]
     ligands = [synth.make_ligand(1, 400 + i, n, min(12, n // 4), 8) for i, n in enumerate(atoms)]
@@ -240,20 +243,22 @@ def test_launch_shape_does_not_change_results(dk):
     ligs = dk.dock_create_ligands(pocket, ligands)
     lo, hi = synth.pocket_box(grid)
     stride = 7 + max(l.n_torsions for l in ligands)
-    params = _params(dk, lo, hi, pop_size=75, n_generations=6)
     bounds = [b for b, _, _ in dk.dock_search_shapes(ligs)]
     assert bounds == [16, 32, 48, 64, 96]
-    ref = None
-    for lp in (1, 2, 4, 8):
-        for w in (0, 1, 2, 3):
-            if w * lp > 12:
-                continue   # at most twelve wavefronts per workgroup
-            dk.dock_search_set_shapes(ligs, [(b, lp, w) for b in bounds])
-            got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
-            if ref is None:
-                ref = got
-            for x, y in zip(ref, got):
-                assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (lp, w)
+    for pop in (178, 75):
+        print("case: launch shapes, population", pop, flush=True)
+        params = _params(dk, lo, hi, pop_size=pop, n_generations=6)
+        ref = None
+        for lp in (1, 2, 4, 8):
+            for w in (0, 1, 2, 3):
+                if w * lp > 12:
+                    continue   # at most twelve wavefronts per workgroup
+                dk.dock_search_set_shapes(ligs, [(b, lp, w) for b in bounds])
+                got = [x.cpu().numpy() for x in _run_gpu_search(dk, pocket, ligs, params, len(ligands), stride)[:4]]
+                if ref is None:
+                    ref = got
+                for x, y in zip(ref, got):
+                    assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (pop, lp, w)
     dk.dock_search_autotune(pocket, ligs, params, stride, tune_generations=2)
     for b, lp, w in dk.dock_search_shapes(ligs):
         assert lp in (1, 2, 4, 8) and 1 <= w <= 12 // lp

@@ -165,14 +165,15 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
 // scored by the block's WS wavefronts together.  Every wavefront of the
 // workgroup takes part in every pass (so all of them meet the same barriers);
 // lanes without an individual score individual 0, in bounds, and drop the
-// result.  With TAIL (splits 2 and 4, chosen at launch when the population
+// result.  With TAIL (splits 2, 4 and 8, chosen at launch when the population
 // ends in a short pass), a generation's last pass, when what is left of the
 // population fits in half of each block (32 individuals), scores half blocks
 // instead: lanes l and l + 32 share an individual and each takes half of the
 // pair and atom work, so the tail of the population costs about half a pass
-// (the same energies, bit for bit).  It is a separate instance so that the
-// registers of the half-block code cost nothing where no pass uses it.  The
-// population is worked on in a gene-major copy W (gene j of
+// (the same energies, bit for bit).  With split 8, wavefronts 0-3 score the
+// half block as a split of four, and wavefronts 4-7 only meet its barriers.
+// It is a separate instance so that the registers of the half-block code cost
+// nothing where no pass uses it.  The population is worked on in a gene-major copy W (gene j of
 // individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
 // touch neighbouring words; the caller's individual-major population is read at
 // the start and written back at the end.
@@ -194,10 +195,18 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
   auto score = [&](const float *g, int gs) {
     return score_pose<LAYOUT, WS, 1>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
   };
-  constexpr bool kHalf = TAIL && (WS == 2 || WS == 4);
+  constexpr bool kHalf = TAIL && WS >= 2;
+  constexpr int HWS = WS == 8 ? 4 : WS;   // wavefronts of a block that score a half block
   auto score_half = [&](const float *g, int gs) {
-    if constexpr (kHalf) return score_pose<LAYOUT, WS, 1, true>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
-    else return score(g, gs);
+    if constexpr (kHalf) {
+      if (WS == HWS || h < HWS) return score_pose<LAYOUT, HWS, 1, true>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
+      // the barriers of a pose of the split of four: the reference coordinates,
+      // each torsion, the rigid move, the reduction
+      for (int b = 0; b < H.n_tors + 3; ++b) __syncthreads();
+      return 0.f;
+    } else {
+      return score(g, gs);
+    }
   };
   for (int c = 0; c < P; c += NT) {
     const int i = c + t;
@@ -263,10 +272,11 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
       const int i = c + (half ? (wave / WS) * (kBlock / 2) + (lane & (kBlock / 2 - 1)) : slot);
       const float *gi = T + (i < P ? i : 0);
       const float e = half ? score_half(gi, P) : score(gi, P);
-      if (i < P && (!half || lane < kBlock / 2)) {
+      if (i < P && (!half || (lane < kBlock / 2 && h < HWS))) {
         float ei = E[i];
         if (e <= ei) {
-          copy_genes<WS>(T + i, W + i, h, G, P);
+          if (half) copy_genes<HWS>(T + i, W + i, h, G, P);
+          else copy_genes<WS>(T + i, W + i, h, G, P);
           ei = e;
           if (h == 0) E[i] = e;
         }
@@ -362,8 +372,8 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
   // sized for the bucket's largest ligand, so a larger b can leave fewer
   // wavefronts resident per CU.  Unless the caller fixes b, pick the b that
   // minimises (rounds of resident ligands) x (scoring passes per generation).
-  // splits 2 and 4 have a half-block instance (the same kernel otherwise)
-  constexpr bool kCanTail = WS == 2 || WS == 4;
+  // splits 2, 4 and 8 have a half-block instance (the same kernel otherwise)
+  constexpr bool kCanTail = WS >= 2;
   auto kernel = (const void *)search_kernel<LAYOUT, WS, false>;
   auto kernel_tail = (const void *)search_kernel<LAYOUT, WS, kCanTail>;
   const size_t per_block = search_block_floats(S.lds_atoms, WS) * sizeof(float);
@@ -429,7 +439,7 @@ static hipError_t launch_search_t(const SearchLaunch &S, int32_t n_cu, int32_t b
   const size_t lds = per_block * best_b;
   const int64_t grid = std::min<int64_t>(S.n_order, (int64_t)n_cu * best_groups);
   // the half-block instance when the population ends in a pass of at most
-  // half a pass (splits 2 and 4)
+  // half a pass (splits 2, 4 and 8)
   const int pass = best_b * kBlock, rem = S.p.pop % pass;
   const bool tail = kCanTail && rem > 0 && 2 * rem <= pass;
   *step = "search kernel launch";

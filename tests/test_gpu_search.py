@@ -209,6 +209,38 @@ def test_search_matches_oracle_lockstep_then_distribution(dk, ora):
     assert ks_2samp(gpu_best, ora_best).pvalue > 0.01
 
 
+def test_half_block_search_matches_oracle_lockstep(dk, ora):
+    """Population 150 with one block per workgroup ends every generation with a
+    half-block pass (22 individuals, two lanes each).  With splits 2, 4 and 8
+    the GPU search stays in lockstep with the oracle's for at least 10
+    generations (the oracle scores in FP64, so a near-tie selection may flip
+    later), the three splits give the same bits, and every stored energy is the
+    oracle's score of its stored genotype."""
+    ff, rec, grid, maps = system(0)
+    lig = synth.make_ligand(1, 0, 24, 6, 8)
+    pocket = dk.dock_create_pocket(grid, maps, ff)
+    ligs = dk.dock_create_ligands(pocket, [lig])
+    lo, hi = synth.pocket_box(grid)
+    bounds = [b for b, _, _ in dk.dock_search_shapes(ligs)]
+    from tests._systems import assert_energies_match
+    runs = []
+    for split in (4, 2, 8):
+        print("case: population 150, split", split, flush=True)
+        dk.dock_search_set_shapes(ligs, [(b, split, 1) for b in bounds])
+        if split == 4:
+            gb, ob, first = _lockstep(dk, ora, pocket, ligs, grid, maps, ff, [lig], lo, hi, 13, 150, 30, 3)
+            print("population 150: first diverging generation", int(first[0]), "gpu best", gb[0], "oracle best",
+                  ob[0], flush=True)
+            assert first[0] < 0 or first[0] >= 10, first
+        r = _run_gpu_search(dk, pocket, ligs, _params(dk, lo, hi, pop_size=150, n_generations=30, seed=3), 1, 13)
+        runs.append([x.cpu().numpy() for x in r[:4]])
+    for other in runs[1:]:
+        for x, y in zip(runs[0], other):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    ref = ora.score_poses(grid, maps, ff, [lig], runs[0][0][0])
+    assert_energies_match(runs[0][1][0], ref)
+
+
 def test_gen_reached(dk):
     import torch
     ff, rec, grid, maps = system(0)

@@ -7,7 +7,9 @@
 // pose l, and wavefront h of the block takes its share of the atoms and of the
 // pair records.  All ligand data (atoms, torsions, pairs) is uniform across a
 // wavefront and arrives through scalar loads, so every loop below is a scalar
-// loop and every pair record is an instruction operand as loaded.  A pose's
+// loop and every pair record is an instruction operand as loaded (in a half
+// block, described at score_pose, records and atoms differ between the two lane
+// halves and arrive by vector loads; the loops stay scalar).  A pose's
 // atom coordinates live in an LDS column shared by its WS lanes: coordinate c
 // of atom i at my[(3 i + c) * 64], so the lanes that read the same atom hit
 // consecutive dwords.

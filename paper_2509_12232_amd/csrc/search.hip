@@ -173,10 +173,10 @@ __global__ void de_trials_kernel(LigandsDev L, DEParams p, int gen, int g_stride
 // (the same energies, bit for bit).  With split 8, wavefronts 0-3 score the
 // half block as a split of four, and wavefronts 4-7 only meet its barriers.
 // It is a separate instance so that the registers of the half-block code cost
-// nothing where no pass uses it.  The population is worked on in a gene-major copy W (gene j of
-// individual i at W[j * P + i]), as are the trials, so that neighbouring lanes
-// touch neighbouring words; the caller's individual-major population is read at
-// the start and written back at the end.
+// nothing where no pass uses it.  The population is worked on in a gene-major
+// copy W (gene j of individual i at W[j * P + i]), as are the trials, so that
+// neighbouring lanes touch neighbouring words; the caller's individual-major
+// population is read at the start and written back at the end.
 template <int LAYOUT, int WS, bool TAIL>
 __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *red) {
   const int t = threadIdx.x, NT = blockDim.x;
@@ -200,8 +200,8 @@ __device__ void search_ligand(const SearchLaunch &S, int lig, float *my, float *
   auto score_half = [&](const float *g, int gs) {
     if constexpr (kHalf) {
       if (WS == HWS || h < HWS) return score_pose<LAYOUT, HWS, 1, true>(S.L, S.geom, S.ff, S.maps, H, g, gs, my, red, h);
-      // the barriers of a pose of the split of four: the reference coordinates,
-      // each torsion, the rigid move, the reduction
+      // the barriers that score_pose holds for a split above one (n_tors + 3:
+      // the reference coordinates, each torsion, the rigid move, the reduction)
       for (int b = 0; b < H.n_tors + 3; ++b) __syncthreads();
       return 0.f;
     } else {
